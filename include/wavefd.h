@@ -1,0 +1,233 @@
+/*
+ * wavefd.h - C ABI of an MI355X (gfx950) explicit finite-difference acoustic
+ * propagator: forward modelling, its exact discrete adjoint, the adjoint-state
+ * gradient with optimal checkpointing, and a continuous-batching serving engine.
+ *
+ * The operations follow arxiv 1808.01995 (Louboutin et al., Devito v3.1.0):
+ *   - PDE: m u_tt - Lap u + eta u_t = q, m = 1/c^2 the squared slowness
+ *     (eq. acoustic, eq. fdWE-abc, Section "Boundary conditions");
+ *   - space: centred second differences of even order k = space_order per axis
+ *     (eq. fdSpace), summed into the Laplacian;
+ *   - time: second-order centred difference (eq. fdTime), explicit update
+ *     (eq. eulerfwd) with the damping term differenced centrally:
+ *         a u^{n+1} = 2 m u^n - b u^{n-1} + dt^2 Lap u^n,
+ *         a = m + eta dt/2, b = m - eta dt/2;
+ *   - zero Dirichlet values beyond the computational grid (Section "Acoustic
+ *     forward modelling operator");
+ *   - sources injected and receivers interpolated multilinearly inside the
+ *     containing cell (Section "Sparse point interpolation"); a source sample
+ *     q^n enters u^{n+1} with weight dt^2/a (dt^2/m where eta = 0);
+ *   - adjoint: the transpose A(m)^T, i.e. backward substitution (matrix view in
+ *     Section "Temporal discretization"; eq. Adj);
+ *   - gradient of Phi = 1/2 ||P_r u - d||^2 (eqs. AS, Grad):
+ *         g = - sum_{j=1}^{nt-1} u^j (v^{j-1} - 2 v^j + v^{j+1}) / dt^2,
+ *     with the forward wavefield kept by optimal (revolve) checkpointing
+ *     (Section "Discrete adjoint wave-equation and FWI gradient").
+ *
+ * Conventions shared by every call:
+ *   - Physical grid n[0..ndim-1] nodes with spacing h (m); a damping layer of
+ *     nbl nodes is added outside it on every side, so the computational grid
+ *     has Nc_a = n_a + 2 nbl nodes. Arrays on the computational grid are dense,
+ *     C-order [x][y][z] (3D) or [x][z] (2D), z contiguous, FP32.
+ *   - Units: metres, milliseconds, km/s; m in (ms/m)^2.
+ *   - Coordinates are FP64 metres relative to the physical origin, in the
+ *     order (x, z) or (x, y, z); a point must lie inside the computational grid
+ *     (-nbl h_a <= x_a - origin_a <= (n_a - 1 + nbl) h_a), else WF_E_DOMAIN.
+ *   - Time axis: nt samples t_n = n dt (nt - 1 updates). Wavelets and records
+ *     are [nt][npoints] row-major FP32 device arrays. Record row 0 is P_r u^0 = 0.
+ *   - Damping: eta = sum_a eta_max_a (d_a/nbl)^p, d_a = distance (nodes) from
+ *     the physical grid along axis a, eta_max_a = 3 ln(1/R) / (2 nbl h_a c_ref).
+ *
+ * Ownership: the caller owns every pointer it passes (device buffers and host
+ * coordinate arrays); host arrays are read before the call returns, device
+ * inputs are read by work enqueued on `stream` and outputs are written in
+ * stream order. The library owns only what its handles hold (wavefields,
+ * coefficients, checkpoints, sparse tables), freed by the matching destroy.
+ *
+ * Streams: `stream` is a hipStream_t passed as void*; NULL means the default
+ * stream. Calls enqueue work and return without synchronising, except where
+ * noted. A handle is not thread-safe: use one per host thread.
+ *
+ * Errors: every call returns a wf_status. Argument, shape, CFL, domain and
+ * budget errors are detected on the host before anything is enqueued and leave
+ * no side effect. wf_last_error() returns a message for the calling thread's
+ * most recent failure. No C++ exception crosses this interface.
+ */
+#ifndef WAVEFD_H
+#define WAVEFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int wf_status;
+
+#define WF_OK            0
+#define WF_E_ARG        -1  /* bad argument, shape or order                  */
+#define WF_E_DOMAIN     -2  /* a sparse point lies outside the grid           */
+#define WF_E_CFL        -3  /* dt above the stability limit wf_critical_dt()  */
+#define WF_E_NOMEM      -4  /* device allocation failed                       */
+#define WF_E_BUDGET     -5  /* the request does not fit the HBM budget        */
+#define WF_E_HIP        -6  /* a HIP runtime call failed                      */
+#define WF_E_NONFINITE  -7  /* a non-finite value was produced (validation)   */
+#define WF_E_STATE      -8  /* handle in the wrong state / unknown ticket     */
+
+typedef struct {
+    int     ndim;         /* 2 or 3                                              */
+    int64_t n[3];         /* physical nodes per axis (x, [y,] z)                 */
+    double  h[3];         /* spacing per axis (m)                                */
+    double  origin[3];    /* physical origin (m)                                 */
+    int     nbl;          /* damping-layer width in nodes (>= 0)                 */
+    int     space_order;  /* k: even, 4..16                                      */
+    double  c_ref;        /* damping reference velocity (km/s), > 0              */
+    double  R;            /* nominal reflection coefficient; 0 selects 1e-3      */
+    int     eta_power;    /* damping profile power p (1..4); 0 selects 2         */
+} wf_geom;
+
+typedef struct wf_model  wf_model;   /* opaque, device-resident model          */
+typedef struct wf_engine wf_engine;  /* opaque serving engine                  */
+
+/* Message for the calling thread's last failure ("" if none). The pointer stays
+ * valid until the next call on the same thread. */
+const char* wf_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int wf_version(void);
+
+/* Stability limit of the explicit update (eq. eulerfwd) for this geometry:
+ * dt_crit = 2 / (vmax sqrt(S sum_a h_a^-2)), S = sum of |weights| of the order-k
+ * 1D stencil. Pure host function; returns a negative value on bad input. */
+double wf_critical_dt(const wf_geom* geom, double vmax);
+
+/* Computational-grid shape of `geom` (Nc per axis, 1 for unused axes) and the
+ * number of computational nodes. Pure host function. */
+wf_status wf_geom_shape(const wf_geom* geom, int64_t shape_out[3], int64_t* npoints_out);
+
+/* Create a device-resident model from the squared slowness m on the
+ * computational grid (dense FP32, Nc^D, device pointer, all values > 0 and
+ * finite). The library copies what it needs; m_dev may be freed after the work
+ * enqueued on `stream` has run. */
+wf_status wf_model_create(const wf_geom* geom, const float* m_dev, void* stream,
+                          wf_model** out);
+
+/* Replace the model's squared slowness (same layout as in create). */
+wf_status wf_model_set_m(wf_model* model, const float* m_dev, void* stream);
+
+/* Device bytes held by the model handle itself (fields, coefficients). */
+int64_t wf_model_bytes(const wf_model* model);
+
+/* Free the model and everything it holds. Synchronises its device work. */
+wf_status wf_model_destroy(wf_model* model);
+
+/* Forward modelling d = P_r A(m)^{-1} P_s^T q (Section "Acoustic forward
+ * modelling operator").
+ *   src_xyz  host FP64 [nsrc][ndim];  src_wav device FP32 [nt][nsrc]
+ *   rec_xyz  host FP64 [nrec][ndim];  rec_out device FP32 [nt][nrec] (written)
+ *   u_save   device FP32 [(nt-1)/save_every + 1][Nc^D] or NULL: receives u^n
+ *            for n = 0, save_every, 2 save_every, ... (dense layout)
+ * nt >= 1, nsrc >= 0, nrec >= 0, 0 < dt <= wf_critical_dt(geom, vmax(m)). */
+wf_status wf_forward(wf_model* model, double dt, int nt,
+                     int nsrc, const double* src_xyz, const float* src_wav,
+                     int nrec, const double* rec_xyz, float* rec_out,
+                     float* u_save, int save_every, void* stream);
+
+/* Adjoint x = P_s A(m)^{-T} P_r^T y (eq. Adj): the exact transpose of
+ * wf_forward with the same arguments. rec_in device FP32 [nt][nrec] (row 0 is
+ * never used), src_out device FP32 [nt][nsrc] (written; row nt-1 is 0). */
+wf_status wf_adjoint(wf_model* model, double dt, int nt,
+                     int nrec, const double* rec_xyz, const float* rec_in,
+                     int nsrc, const double* src_xyz, float* src_out, void* stream);
+
+/* Adjoint-state gradient (eqs. Grad, Adj) of Phi = 1/2 ||P_r u - d_obs||^2 at
+ * the model's m for the given residual r = P_r u - d_obs (device FP32
+ * [nt][nrec]); grad_out device FP32 Nc^D (dense, overwritten).
+ *   n_checkpoints  > 0: revolve with that many stored states (2 fields each);
+ *                  -1 : store every forward wavefield (no recomputation);
+ *                   0 : the largest count that fits hbm_budget_bytes.
+ *   hbm_budget_bytes  bound on the device memory the call may allocate for
+ *                  checkpoints and its temporaries (0: no bound).
+ * Results are bitwise identical for every checkpoint count. */
+wf_status wf_gradient(wf_model* model, double dt, int nt,
+                      int nsrc, const double* src_xyz, const float* src_wav,
+                      int nrec, const double* rec_xyz, const float* residual,
+                      float* grad_out, int n_checkpoints, int64_t hbm_budget_bytes,
+                      void* stream);
+
+/* Number of forward time steps the revolve schedule of wf_gradient performs
+ * for `steps` updates and `snaps` stored states (steps >= 1, snaps >= 1):
+ * the optimal count r l - C(s + r, r - 1) of Griewank and Walther. Pure host
+ * function; -1 on bad input. */
+int64_t wf_revolve_forward_steps(int64_t steps, int snaps);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (tracing aid).                                               */
+/* ------------------------------------------------------------------------ */
+
+#define WF_KERNEL_STEP    0   /* the fused time-step kernel                   */
+#define WF_KERNEL_INJECT  1   /* sparse injection                              */
+#define WF_KERNEL_SAMPLE  2   /* sparse interpolation                          */
+
+/* While enabled (process-wide), every launch of the three kernels above is
+ * bracketed by a pair of HIP events recorded on the stream it runs on. */
+wf_status wf_profile_enable(int on);
+
+/* Synchronise on the recorded events and return, for kernel `kind`, the summed
+ * device time in ms and the number of launches since the last reset; reset != 0
+ * clears the record of every kind. */
+wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int reset);
+
+/* ------------------------------------------------------------------------ */
+/* Serving engine: continuous batching of forward and gradient requests.     */
+/* ------------------------------------------------------------------------ */
+
+#define WF_REQ_FORWARD  0
+#define WF_REQ_GRADIENT 1
+
+typedef struct {
+    int            kind;         /* WF_REQ_FORWARD or WF_REQ_GRADIENT            */
+    wf_geom        geom;
+    const float*   m_dev;        /* squared slowness, computational grid (device) */
+    double         dt;
+    int            nt;
+    int            nsrc;
+    const double*  src_xyz;      /* host, copied at submit                        */
+    const float*   src_wav;      /* device [nt][nsrc]                             */
+    int            nrec;
+    const double*  rec_xyz;      /* host, copied at submit                        */
+    const float*   d_obs;        /* device [nt][nrec], gradient requests only     */
+    float*         rec_out;      /* device [nt][nrec]: modelled data (written)    */
+    float*         grad_out;     /* device Nc^D, gradient requests only (written) */
+    double*        misfit_out;   /* host, gradient requests only (written at completion) */
+} wf_request;
+
+/* Create an engine that may hold at most `hbm_budget_bytes` of device memory
+ * for admitted requests and run at most `max_slots` requests at once. It owns
+ * its own HIP streams on the current device. */
+wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** out);
+
+/* Queue a request; returns at once with a ticket. The request's device inputs
+ * must stay valid and unchanged until the ticket is reported done. Requests
+ * that could never fit the budget fail here with WF_E_BUDGET. */
+wf_status wf_engine_submit(wf_engine* engine, const wf_request* req, uint64_t* ticket);
+
+/* Advance the engine: admit queued requests as slots and memory free up, issue
+ * their next batch of steps, and report finished tickets (up to `cap`) with
+ * their status. Non-blocking unless `wait_ms` > 0, in which case it waits up to
+ * that long for at least one completion. */
+wf_status wf_engine_poll(wf_engine* engine, uint64_t* done_tickets, wf_status* done_status,
+                         int cap, int* n_done, int wait_ms);
+
+/* Engine statistics: queued, running, completed counts and device bytes in use. */
+wf_status wf_engine_stats(const wf_engine* engine, int64_t* queued, int64_t* running,
+                          int64_t* completed, int64_t* bytes_in_use);
+
+/* Wait for every request, then free the engine. */
+wf_status wf_engine_destroy(wf_engine* engine);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVEFD_H */

@@ -1,0 +1,269 @@
+"""ctypes binding of include/wavefd.h (libwavefd.so, built for gfx950).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels. Device arrays are torch tensors on the GPU (float32, contiguous);
+host coordinate arrays are float64 numpy arrays; streams default to torch's
+current stream. The functions keep the C names.
+
+Importing this module loads the library and raises if it is missing: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwavefd.so")
+
+WF_OK = 0
+WF_E_ARG = -1
+WF_E_DOMAIN = -2
+WF_E_CFL = -3
+WF_E_NOMEM = -4
+WF_E_BUDGET = -5
+WF_E_HIP = -6
+WF_E_NONFINITE = -7
+WF_E_STATE = -8
+_NAMES = {0: "WF_OK", -1: "WF_E_ARG", -2: "WF_E_DOMAIN", -3: "WF_E_CFL", -4: "WF_E_NOMEM",
+          -5: "WF_E_BUDGET", -6: "WF_E_HIP", -7: "WF_E_NONFINITE", -8: "WF_E_STATE"}
+
+WF_REQ_FORWARD = 0
+WF_REQ_GRADIENT = 1
+
+
+class WaveFDError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__("%s: %s" % (_NAMES.get(status, str(status)), message))
+
+
+class wf_geom(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int),
+                ("n", ctypes.c_int64 * 3),
+                ("h", ctypes.c_double * 3),
+                ("origin", ctypes.c_double * 3),
+                ("nbl", ctypes.c_int),
+                ("space_order", ctypes.c_int),
+                ("c_ref", ctypes.c_double),
+                ("R", ctypes.c_double),
+                ("eta_power", ctypes.c_int)]
+
+
+class wf_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int),
+                ("geom", wf_geom),
+                ("m_dev", ctypes.c_void_p),
+                ("dt", ctypes.c_double),
+                ("nt", ctypes.c_int),
+                ("nsrc", ctypes.c_int),
+                ("src_xyz", ctypes.c_void_p),
+                ("src_wav", ctypes.c_void_p),
+                ("nrec", ctypes.c_int),
+                ("rec_xyz", ctypes.c_void_p),
+                ("d_obs", ctypes.c_void_p),
+                ("rec_out", ctypes.c_void_p),
+                ("grad_out", ctypes.c_void_p),
+                ("misfit_out", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libwavefd.so is not built (run __graft_entry__.build() or "
+                          "python paper_1808_01995_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    sig = {
+        "wf_last_error": (ctypes.c_char_p, []),
+        "wf_version": (I, []),
+        "wf_critical_dt": (D, [ctypes.POINTER(wf_geom), D]),
+        "wf_geom_shape": (I, [ctypes.POINTER(wf_geom), P, P]),
+        "wf_model_create": (I, [ctypes.POINTER(wf_geom), P, P, P]),
+        "wf_model_set_m": (I, [P, P, P]),
+        "wf_model_bytes": (I64, [P]),
+        "wf_model_destroy": (I, [P]),
+        "wf_forward": (I, [P, D, I, I, P, P, I, P, P, P, I, P]),
+        "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
+        "wf_gradient": (I, [P, D, I, I, P, P, I, P, P, P, I, I64, P]),
+        "wf_revolve_forward_steps": (I64, [I64, I]),
+        "wf_engine_create": (I, [I64, I, P]),
+        "wf_engine_submit": (I, [P, ctypes.POINTER(wf_request), P]),
+        "wf_engine_poll": (I, [P, P, P, I, P, I]),
+        "wf_engine_stats": (I, [P, P, P, P, P]),
+        "wf_engine_destroy": (I, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+# every symbol declared in include/wavefd.h
+EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
+           "wf_model_set_m", "wf_model_bytes", "wf_model_destroy", "wf_forward", "wf_adjoint",
+           "wf_gradient", "wf_revolve_forward_steps", "wf_engine_create", "wf_engine_submit",
+           "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
+
+
+def _check(st: int):
+    if st != WF_OK:
+        raise WaveFDError(st, lib.wf_last_error().decode(errors="replace"))
+
+
+def make_geom(shape: Sequence[int], spacing: Sequence[float], nbl: int, space_order: int,
+              c_ref: float, origin: Optional[Sequence[float]] = None, R: float = 0.0,
+              eta_power: int = 0) -> wf_geom:
+    """Geometry of a physical grid `shape` (2 or 3 axes) with an nbl-node
+    damping layer outside it on every side."""
+    g = wf_geom()
+    nd = len(shape)
+    g.ndim = nd
+    for a in range(nd):
+        g.n[a] = int(shape[a])
+        g.h[a] = float(spacing[a])
+        g.origin[a] = float(origin[a]) if origin is not None else 0.0
+    for a in range(nd, 3):
+        g.n[a] = 1
+        g.h[a] = 1.0
+    g.nbl = int(nbl)
+    g.space_order = int(space_order)
+    g.c_ref = float(c_ref)
+    g.R = float(R)
+    g.eta_power = int(eta_power)
+    return g
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a contiguous float32 CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 tensor")
+    return t.data_ptr()
+
+
+def _host(xyz) -> tuple:
+    if xyz is None:
+        return 0, None, None
+    a = np.ascontiguousarray(np.atleast_2d(np.asarray(xyz, dtype=np.float64)))
+    if a.size == 0:
+        return 0, None, a
+    return a.shape[0], a.ctypes.data_as(ctypes.c_void_p), a
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def wf_version() -> int:
+    return lib.wf_version()
+
+
+def wf_last_error() -> str:
+    return lib.wf_last_error().decode(errors="replace")
+
+
+def wf_critical_dt(geom: wf_geom, vmax: float) -> float:
+    v = lib.wf_critical_dt(ctypes.byref(geom), float(vmax))
+    if v < 0:
+        raise WaveFDError(WF_E_ARG, wf_last_error())
+    return v
+
+
+def wf_geom_shape(geom: wf_geom):
+    shp = (ctypes.c_int64 * 3)()
+    n = ctypes.c_int64()
+    _check(lib.wf_geom_shape(ctypes.byref(geom), shp, ctypes.byref(n)))
+    return tuple(int(shp[a]) for a in range(geom.ndim)), int(n.value)
+
+
+def wf_model_create(geom: wf_geom, m, stream=None) -> ctypes.c_void_p:
+    out = ctypes.c_void_p()
+    _check(lib.wf_model_create(ctypes.byref(geom), _ptr(m), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def wf_model_set_m(model, m, stream=None):
+    _check(lib.wf_model_set_m(model, _ptr(m), _stream(stream)))
+
+
+def wf_model_bytes(model) -> int:
+    return int(lib.wf_model_bytes(model))
+
+
+def wf_model_destroy(model):
+    _check(lib.wf_model_destroy(model))
+
+
+def wf_forward(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, rec_out,
+               u_save=None, save_every: int = 1, stream=None):
+    ns, sp, _sa = _host(src_xyz)
+    nr, rp, _ra = _host(rec_xyz)
+    _check(lib.wf_forward(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None,
+                          nr, rp, _ptr(rec_out) if nr else None, _ptr(u_save), int(save_every),
+                          _stream(stream)))
+
+
+def wf_adjoint(model, dt: float, nt: int, rec_xyz, rec_in, src_xyz, src_out, stream=None):
+    nr, rp, _ra = _host(rec_xyz)
+    ns, sp, _sa = _host(src_xyz)
+    _check(lib.wf_adjoint(model, float(dt), int(nt), nr, rp, _ptr(rec_in) if nr else None,
+                          ns, sp, _ptr(src_out) if ns else None, _stream(stream)))
+
+
+def wf_gradient(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, residual, grad_out,
+                n_checkpoints: int = 0, hbm_budget_bytes: int = 0, stream=None):
+    ns, sp, _sa = _host(src_xyz)
+    nr, rp, _ra = _host(rec_xyz)
+    _check(lib.wf_gradient(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None,
+                           nr, rp, _ptr(residual) if nr else None, _ptr(grad_out),
+                           int(n_checkpoints), int(hbm_budget_bytes), _stream(stream)))
+
+
+def wf_revolve_forward_steps(steps: int, snaps: int) -> int:
+    return int(lib.wf_revolve_forward_steps(int(steps), int(snaps)))
+
+
+def wf_engine_create(hbm_budget_bytes: int, max_slots: int):
+    out = ctypes.c_void_p()
+    _check(lib.wf_engine_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(out)))
+    return out
+
+
+def wf_engine_submit(engine, req: wf_request) -> int:
+    t = ctypes.c_uint64()
+    _check(lib.wf_engine_submit(engine, ctypes.byref(req), ctypes.byref(t)))
+    return int(t.value)
+
+
+def wf_engine_poll(engine, cap: int = 64, wait_ms: int = 0):
+    tickets = (ctypes.c_uint64 * cap)()
+    status = (ctypes.c_int * cap)()
+    n = ctypes.c_int()
+    _check(lib.wf_engine_poll(engine, tickets, status, int(cap), ctypes.byref(n), int(wait_ms)))
+    return [(int(tickets[i]), int(status[i])) for i in range(n.value)]
+
+
+def wf_engine_stats(engine):
+    q, r, c, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.wf_engine_stats(engine, ctypes.byref(q), ctypes.byref(r), ctypes.byref(c), ctypes.byref(b)))
+    return {"queued": q.value, "running": r.value, "completed": c.value, "bytes_in_use": b.value}
+
+
+def wf_engine_destroy(engine):
+    _check(lib.wf_engine_destroy(engine))

@@ -1,0 +1,90 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+// Everything here is device-side data layout and launch plumbing; the public
+// C ABI is include/wavefd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace wf {
+
+constexpr int kMaxHalf = 8;   // space order up to 16
+
+// Parameters of one time step of the fused update
+//   out = (2 cur - (1 - g) old + kap * Lap(cur)) / (1 + g),  g = eta kap / (2 dt)
+// on a pitched field layout: element (x, y, z) at x*sx + y*sy + z, sy = pitch
+// (a multiple of 4 floats, >= nz rounded up to 4; the pad is kept at zero).
+// `out` may alias `old` (in-place update; every element of old is read by the
+// thread that then writes the same element of out).
+// With imaging on (adjoint sweeps of the gradient): grad -= ufwd * (out - 2 cur
+// + old) / dt^2, using `out` before any receiver injection.
+struct StepParams {
+    const float* cur;
+    const float* old;
+    float* out;
+    const float* kap;
+    const float* etax;   // per-axis damping profiles (eta = etax + etay + etaz)
+    const float* etay;   // unused in 2D
+    const float* etaz;
+    float* grad;
+    const float* ufwd;
+    int nx, ny, nz;      // ny == 1 in 2D
+    int64_t sx, sy;      // strides in floats
+    int cx;              // x-chunk length per block
+    int ntz, nty, nchunks, nblocks;
+    float c0;            // alpha_0 * sum_a 1/h_a^2
+    float wx[kMaxHalf + 1], wy[kMaxHalf + 1], wz[kMaxHalf + 1];  // alpha_j / h_a^2
+    float inv2dt;
+    float idt2;
+};
+
+// Tile shapes chosen by the launcher (threads along z carry 4 points each).
+struct TileShape {
+    int bz, by;   // threads along z and y per block
+};
+
+TileShape step_tile(int ndim, int half);
+// Fill ntz/nty/nchunks/nblocks/cx for the given chunk length (0 = automatic).
+void step_plan(StepParams& p, int ndim, int half, int cx_request);
+hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s);
+
+// Sparse injection at unique nodes (deterministic, no atomics):
+//   field[off[i]] += scale_i * sum_{e in seg i} w[e] * vals[pt[e]],
+//   scale_i = kap / (1 + eta_i kap / (2 dt)) at that node;
+// with imaging: grad[off[i]] -= ufwd[off[i]] * that increment / dt^2.
+struct InjectParams {
+    float* field;
+    const float* kap;
+    const int64_t* off;
+    const float* eta;
+    const int* seg;      // nnodes + 1 offsets into pt/w
+    const int* pt;
+    const float* w;
+    const float* vals;   // one row of the [nt][npts] series
+    float* grad;
+    const float* ufwd;
+    int nnodes;
+    float inv2dt, idt2;
+};
+hipError_t launch_inject(const InjectParams& p, hipStream_t s);
+
+// out[i] = sum_k w[i*K + k] * field[off[i*K + k]]
+hipError_t launch_sample(const float* field, const int64_t* off, const float* w, int npts,
+                         int K, float* out, hipStream_t s);
+
+// kap (pitched) = dt^2 / m (dense), computed in FP64; pad set to zero.
+hipError_t launch_coef(const float* m_dense, float* kap, int nx, int ny, int nz, int64_t sx,
+                       int64_t sy, double dt, hipStream_t s);
+// pitched -> dense and dense -> pitched copies (pad of the pitched side zeroed).
+hipError_t launch_unpitch(const float* src, float* dst, int nx, int ny, int nz, int64_t sx,
+                          int64_t sy, hipStream_t s);
+hipError_t launch_pitch(const float* src, float* dst, int nx, int ny, int nz, int64_t sx,
+                        int64_t sy, hipStream_t s);
+hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s);
+hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+// count of non-finite values in x[0..n) added to *count
+hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count, hipStream_t s);
+// min and max of m over n values into out[0], out[1] (out pre-filled by caller)
+hipError_t launch_minmax(const float* x, int64_t n, float* out2, hipStream_t s);
+
+}  // namespace wf

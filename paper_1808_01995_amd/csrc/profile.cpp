@@ -1,0 +1,110 @@
+// Per-kernel device timing with HIP events (enabled on demand).
+#include <mutex>
+#include <vector>
+
+#include "runtime.h"
+
+namespace wf {
+
+namespace {
+
+struct Rec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;          // recorded, not yet read
+std::vector<hipEvent_t> g_free;   // reusable events
+double g_ms[3] = {0, 0, 0};
+int64_t g_n[3] = {0, 0, 0};
+
+hipEvent_t get_event() {
+    if (!g_free.empty()) {
+        hipEvent_t e = g_free.back();
+        g_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Fold finished records into the totals (caller holds the lock).
+wf_status drain(bool wait) {
+    size_t keep = 0;
+    for (size_t i = 0; i < g_recs.size(); ++i) {
+        Rec& r = g_recs[i];
+        if (wait) {
+            if (hipEventSynchronize(r.b) != hipSuccess) return fail(WF_E_HIP, "event sync");
+        } else if (hipEventQuery(r.b) != hipSuccess) {
+            g_recs[keep++] = r;
+            continue;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.kind >= 0 && r.kind < 3) {
+            g_ms[r.kind] += ms;
+            g_n[r.kind] += 1;
+        }
+        g_free.push_back(r.a);
+        g_free.push_back(r.b);
+    }
+    g_recs.resize(keep);
+    (void)hipGetLastError();
+    return WF_OK;
+}
+
+}  // namespace
+
+ProfScope::ProfScope(int k, hipStream_t st) : kind(k), s(st) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on) return;
+    if (g_recs.size() > 4096) drain(false);
+    hipEvent_t a = get_event(), b = get_event();
+    if (!a || !b) return;
+    if (hipEventRecord(a, s) != hipSuccess) return;
+    g_recs.push_back({kind, a, b});
+    slot = (int)g_recs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    // find our record (drain() may have compacted the vector meanwhile only for
+    // finished records, and ours has no stop event recorded yet)
+    for (size_t i = g_recs.size(); i-- > 0;)
+        if (g_recs[i].kind == kind && (int)i <= slot) {
+            (void)hipEventRecord(g_recs[i].b, s);
+            return;
+        }
+}
+
+}  // namespace wf
+
+using namespace wf;
+
+extern "C" {
+
+wf_status wf_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_on = on != 0;
+    return WF_OK;
+}
+
+wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int reset) {
+    if (kind < 0 || kind > 2) return fail(WF_E_ARG, "unknown kernel kind %d", kind);
+    std::lock_guard<std::mutex> lk(g_mu);
+    wf_status st = drain(true);
+    if (st != WF_OK) return st;
+    if (total_ms) *total_ms = g_ms[kind];
+    if (launches) *launches = g_n[kind];
+    if (reset)
+        for (int k = 0; k < 3; ++k) {
+            g_ms[k] = 0.0;
+            g_n[k] = 0;
+        }
+    return WF_OK;
+}
+
+}

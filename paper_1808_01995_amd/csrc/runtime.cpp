@@ -1,0 +1,429 @@
+// Host runtime behind include/wavefd.h: models, sparse-point tables, the time
+// loops of forward, adjoint and gradient, and the error plumbing of the C ABI.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace wf {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+wf_status fail(wf_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+const char* last_error() { return g_err.c_str(); }
+void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------
+// finite-difference weights (eq. fdSpace): centred second derivative of order
+// k = 2M, alpha_j = 2 (-1)^{j+1} (M!)^2 / (j^2 (M-j)! (M+j)!), alpha_0 = -2 sum.
+// Evaluated as a product of small ratios in long double.
+// ---------------------------------------------------------------------------
+void fd_weights(int half, double* alpha) {
+    long double s = 0.0L;
+    for (int j = 1; j <= half; ++j) {
+        // (M!)^2 / ((M-j)! (M+j)!) = prod_{i=1}^{j} (M - j + i) / (M + i)
+        long double r = 1.0L;
+        for (int i = 1; i <= j; ++i) r *= (long double)(half - j + i) / (long double)(half + i);
+        long double a = 2.0L * r / ((long double)j * (long double)j);
+        if ((j & 1) == 0) a = -a;
+        alpha[j] = (double)a;
+        s += a;
+    }
+    alpha[0] = (double)(-2.0L * s);
+}
+
+double abs_weight_sum(int half) {
+    double a[kMaxHalf + 1];
+    fd_weights(half, a);
+    double s = std::fabs(a[0]);
+    for (int j = 1; j <= half; ++j) s += 2.0 * std::fabs(a[j]);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+wf_status check_geom(const wf_geom* g) {
+    if (!g) return fail(WF_E_ARG, "geometry is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(WF_E_ARG, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->space_order < 4 || g->space_order > 2 * kMaxHalf || (g->space_order & 1))
+        return fail(WF_E_ARG, "space_order must be even in [4, %d] (got %d)", 2 * kMaxHalf,
+                    g->space_order);
+    if (g->nbl < 0 || g->nbl > 4096) return fail(WF_E_ARG, "nbl out of range (%d)", g->nbl);
+    for (int a = 0; a < g->ndim; ++a) {
+        if (g->n[a] < 2) return fail(WF_E_ARG, "n[%d] must be >= 2", a);
+        if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return fail(WF_E_ARG, "h[%d] must be > 0", a);
+        if (!std::isfinite(g->origin[a])) return fail(WF_E_ARG, "origin[%d] not finite", a);
+        if (g->n[a] + 2 * (int64_t)g->nbl > (int64_t)1 << 20) return fail(WF_E_ARG, "axis %d too long", a);
+    }
+    if (!(g->c_ref > 0.0) || !std::isfinite(g->c_ref)) return fail(WF_E_ARG, "c_ref must be > 0");
+    if (g->R < 0.0 || g->R >= 1.0) return fail(WF_E_ARG, "R must be in [0, 1)");
+    if (g->eta_power < 0 || g->eta_power > 4) return fail(WF_E_ARG, "eta_power must be in [0, 4]");
+    // the pitched field must be addressable
+    int64_t nx = g->n[0] + 2 * g->nbl, nz = g->n[g->ndim - 1] + 2 * g->nbl;
+    int64_t ny = g->ndim == 3 ? g->n[1] + 2 * g->nbl : 1;
+    if (nx * ny * (nz + 64) > ((int64_t)1 << 40)) return fail(WF_E_ARG, "grid too large");
+    return WF_OK;
+}
+
+void comp_shape(const wf_geom* g, int64_t* nx, int64_t* ny, int64_t* nz) {
+    *nx = g->n[0] + 2 * g->nbl;
+    *ny = g->ndim == 3 ? g->n[1] + 2 * g->nbl : 1;
+    *nz = g->n[g->ndim - 1] + 2 * g->nbl;
+}
+
+double critical_dt(const wf_geom* g, double vmax) {
+    double inv = 0.0;
+    for (int a = 0; a < g->ndim; ++a) inv += 1.0 / (g->h[a] * g->h[a]);
+    return 2.0 / (vmax * std::sqrt(abs_weight_sum(g->space_order / 2) * inv));
+}
+
+// Per-axis damping profile on the computational grid (Section "Boundary
+// conditions"): eta_a(c) = eta_max_a (d/nbl)^p, d = nodes outside the physical
+// range [nbl, nbl + n - 1], eta_max_a = 3 ln(1/R) / (2 nbl h_a c_ref).
+std::vector<float> eta_profile(const wf_geom* g, int axis) {
+    const int64_t n = g->n[axis];
+    const int nbl = g->nbl;
+    const int64_t Nc = n + 2 * (int64_t)nbl;
+    std::vector<float> e((size_t)Nc, 0.0f);
+    if (nbl == 0) return e;
+    const double R = g->R > 0.0 ? g->R : 1e-3;
+    const int p = g->eta_power > 0 ? g->eta_power : 2;
+    const double emax = 3.0 * std::log(1.0 / R) / (2.0 * nbl * g->h[axis] * g->c_ref);
+    for (int64_t c = 0; c < Nc; ++c) {
+        double d = 0.0;
+        if (c < nbl) d = (double)(nbl - c);
+        else if (c > nbl + n - 1) d = (double)(c - (nbl + n - 1));
+        e[(size_t)c] = (float)(emax * std::pow(d / nbl, p));
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+wf_status DevBuf::alloc(int64_t nbytes) {
+    reset();
+    if (nbytes <= 0) return WF_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(WF_E_NOMEM, "hipMalloc(%lld bytes): %s", (long long)nbytes, hipGetErrorString(e));
+    }
+    ptr = p;
+    bytes = nbytes;
+    return WF_OK;
+}
+wf_status DevBuf::upload(const void* host, int64_t nbytes) {
+    wf_status st = alloc(nbytes);
+    if (st != WF_OK) return st;
+    if (nbytes <= 0) return WF_OK;
+    hipError_t e = hipMemcpy(ptr, host, (size_t)nbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(WF_E_HIP, "hipMemcpy H2D: %s", hipGetErrorString(e));
+    return WF_OK;
+}
+
+wf_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return WF_OK;
+    (void)hipGetLastError();
+    return fail(WF_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// fields
+// ---------------------------------------------------------------------------
+void Layout::init(const wf_geom* g) {
+    int64_t x, y, z;
+    comp_shape(g, &x, &y, &z);
+    ndim = g->ndim;
+    nx = (int)x;
+    ny = (int)y;
+    nz = (int)z;
+    // z rows padded to whole 64-byte segments; a multiple of 4 floats is what
+    // the vector loads need, the rest keeps rows on cache-line boundaries
+    int align = 16;
+    if (const char* s = std::getenv("WAVEFD_PITCH_ALIGN")) {
+        int v = std::atoi(s);
+        if (v >= 4 && v <= 256 && (v % 4) == 0) align = v;
+    }
+    sy = ((int64_t)nz + align - 1) / align * align;
+    sx = sy * ny;
+    elems = sx * nx;
+    npoints = (int64_t)nx * ny * nz;
+}
+
+// ---------------------------------------------------------------------------
+// sparse points (Section "Sparse point interpolation"): multilinear weights in
+// the containing cell, computed in FP64 on the host.
+// ---------------------------------------------------------------------------
+wf_status build_points(const wf_geom* g, const Layout& L, int npts, const double* xyz,
+                       std::vector<int64_t>& off, std::vector<float>& w,
+                       std::vector<float>* eta_node) {
+    const int D = g->ndim;
+    const int K = 1 << D;
+    off.assign((size_t)npts * K, 0);
+    w.assign((size_t)npts * K, 0.0f);
+    if (eta_node) eta_node->assign((size_t)npts * K, 0.0f);
+    std::vector<std::vector<float>> prof;
+    if (eta_node)
+        for (int a = 0; a < D; ++a) prof.push_back(eta_profile(g, a));
+    const int64_t Nc[3] = {L.nx, D == 3 ? L.ny : L.nz, L.nz};
+    const int64_t stride[3] = {L.sx, D == 3 ? L.sy : 1, 1};
+    for (int p = 0; p < npts; ++p) {
+        int64_t base[3];
+        double frac[3];
+        for (int a = 0; a < D; ++a) {
+            const double x = xyz[(size_t)p * D + a];
+            if (!std::isfinite(x)) return fail(WF_E_DOMAIN, "point %d: coordinate not finite", p);
+            const double s = (x - g->origin[a]) / g->h[a] + g->nbl;
+            if (s < 0.0 || s > (double)(Nc[a] - 1))
+                return fail(WF_E_DOMAIN, "point %d lies outside the computational grid on axis %d", p, a);
+            int64_t i = (int64_t)std::floor(s);
+            double f = s - (double)i;
+            if (i >= Nc[a] - 1) {
+                i = Nc[a] - 2;
+                f = 1.0;
+            }
+            base[a] = i;
+            frac[a] = f;
+        }
+        for (int k = 0; k < K; ++k) {
+            int64_t o = 0;
+            double wt = 1.0;
+            float e = 0.0f;
+            for (int a = 0; a < D; ++a) {
+                const int bit = (k >> (D - 1 - a)) & 1;
+                o += (base[a] + bit) * stride[a];
+                wt *= bit ? frac[a] : 1.0 - frac[a];
+                if (eta_node) e += prof[a][(size_t)(base[a] + bit)];
+            }
+            off[(size_t)p * K + k] = o;
+            w[(size_t)p * K + k] = (float)wt;
+            if (eta_node) (*eta_node)[(size_t)p * K + k] = e;
+        }
+    }
+    return WF_OK;
+}
+
+wf_status PointSet::build(const wf_geom* g, const Layout& L, int npts_, const double* xyz) {
+    npts = npts_;
+    K = 1 << g->ndim;
+    nnodes = 0;
+    if (npts <= 0) return WF_OK;
+    std::vector<int64_t> off;
+    std::vector<float> w, e;
+    wf_status st = build_points(g, L, npts, xyz, off, w, &e);
+    if (st != WF_OK) return st;
+    // sampling table: as is
+    if ((st = d_off.upload(off.data(), (int64_t)off.size() * 8)) != WF_OK) return st;
+    if ((st = d_w.upload(w.data(), (int64_t)w.size() * 4)) != WF_OK) return st;
+    // injection table: entries grouped by node, in (point, corner) order inside
+    // a node, so every node is summed by one thread in a fixed order
+    const size_t ne = off.size();
+    std::vector<size_t> idx(ne);
+    for (size_t i = 0; i < ne; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return off[a] < off[b]; });
+    std::vector<int64_t> noff;
+    std::vector<float> neta, ew;
+    std::vector<int> seg, ept;
+    for (size_t t = 0; t < ne; ++t) {
+        const size_t i = idx[t];
+        if (t == 0 || off[i] != off[idx[t - 1]]) {
+            seg.push_back((int)t);
+            noff.push_back(off[i]);
+            neta.push_back(e[i]);
+        }
+        ept.push_back((int)(i / K));
+        ew.push_back(w[i]);
+    }
+    seg.push_back((int)ne);
+    nnodes = (int)noff.size();
+    if ((st = d_noff.upload(noff.data(), (int64_t)noff.size() * 8)) != WF_OK) return st;
+    if ((st = d_neta.upload(neta.data(), (int64_t)neta.size() * 4)) != WF_OK) return st;
+    if ((st = d_seg.upload(seg.data(), (int64_t)seg.size() * 4)) != WF_OK) return st;
+    if ((st = d_ept.upload(ept.data(), (int64_t)ept.size() * 4)) != WF_OK) return st;
+    if ((st = d_ew.upload(ew.data(), (int64_t)ew.size() * 4)) != WF_OK) return st;
+    return WF_OK;
+}
+
+uint64_t hash_points(int npts, int D, const double* xyz) {
+    uint64_t h = 1469598103934665603ull ^ (uint64_t)npts ^ ((uint64_t)D << 40);
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(xyz);
+    const size_t n = (size_t)npts * D * sizeof(double);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace wf
+
+// ===========================================================================
+// model
+// ===========================================================================
+using namespace wf;
+
+wf_status Model::init(const wf_geom* g, const float* m_dev, hipStream_t s) {
+    geom = *g;
+    half = g->space_order / 2;
+    L.init(g);
+    fd_weights(half, alpha);
+    wf_status st;
+    const int64_t fb = L.elems * 4 + 256;
+    if ((st = d_m.alloc(L.npoints * 4)) != WF_OK) return st;
+    if ((st = d_kap.alloc(fb)) != WF_OK) return st;
+    if ((st = d_u[0].alloc(fb)) != WF_OK) return st;
+    if ((st = d_u[1].alloc(fb)) != WF_OK) return st;
+    std::vector<float> ex = eta_profile(g, 0);
+    std::vector<float> ey = g->ndim == 3 ? eta_profile(g, 1) : std::vector<float>(1, 0.0f);
+    std::vector<float> ez = eta_profile(g, g->ndim - 1);
+    if ((st = d_etax.upload(ex.data(), (int64_t)ex.size() * 4)) != WF_OK) return st;
+    if ((st = d_etay.upload(ey.data(), (int64_t)ey.size() * 4)) != WF_OK) return st;
+    if ((st = d_etaz.upload(ez.data(), (int64_t)ez.size() * 4)) != WF_OK) return st;
+    if ((st = d_scratch.alloc(256)) != WF_OK) return st;
+    return set_m(m_dev, s);
+}
+
+wf_status Model::set_m(const float* m_dev, hipStream_t s) {
+    if (!m_dev) return fail(WF_E_ARG, "m is NULL");
+    wf_status st;
+    if ((st = hip_check(hipMemcpyAsync(d_m.f(), m_dev, (size_t)L.npoints * 4,
+                                       hipMemcpyDeviceToDevice, s), "copy m")) != WF_OK)
+        return st;
+    // min / max of m (for the stability check) and validity of every value
+    unsigned int init3[3] = {0x7f7fffffu, 0u, 0u};
+    unsigned int* d3 = reinterpret_cast<unsigned int*>(d_scratch.ptr);
+    if ((st = hip_check(hipMemcpyAsync(d3, init3, sizeof init3, hipMemcpyHostToDevice, s), "init minmax")) != WF_OK)
+        return st;
+    if ((st = hip_check(launch_minmax(d_m.f(), L.npoints, reinterpret_cast<float*>(d3), s), "minmax")) != WF_OK)
+        return st;
+    unsigned int out3[3];
+    if ((st = hip_check(hipMemcpyAsync(out3, d3, sizeof out3, hipMemcpyDeviceToHost, s), "read minmax")) != WF_OK)
+        return st;
+    if ((st = hip_check(hipStreamSynchronize(s), "sync")) != WF_OK) return st;
+    if (out3[2] != 0) return fail(WF_E_ARG, "m has %u values that are not positive and finite", out3[2]);
+    float lo, hi;
+    std::memcpy(&lo, &out3[0], 4);
+    std::memcpy(&hi, &out3[1], 4);
+    m_min = lo;
+    m_max = hi;
+    kap_dt = -1.0;   // coefficients must be recomputed
+    return WF_OK;
+}
+
+double Model::vmax() const { return 1.0 / std::sqrt(m_min); }
+
+wf_status Model::ensure_kap(double dt, hipStream_t s) {
+    if (dt == kap_dt) return WF_OK;
+    wf_status st = hip_check(launch_coef(d_m.f(), d_kap.f(), L.nx, L.ny, L.nz, L.sx, L.sy, dt, s), "coef");
+    if (st != WF_OK) return st;
+    kap_dt = dt;
+    return WF_OK;
+}
+
+wf_status Model::check_dt(double dt) const {
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WF_E_ARG, "dt must be > 0");
+    const double dc = critical_dt(&geom, vmax());
+    if (dt > dc * (1.0 + 1e-12))
+        return fail(WF_E_CFL, "dt = %.6g ms exceeds the stability limit %.6g ms (vmax %.4g km/s)", dt, dc, vmax());
+    return WF_OK;
+}
+
+wf_status Model::points(int npts, const double* xyz, const PointSet** out) {
+    *out = nullptr;
+    if (npts < 0) return fail(WF_E_ARG, "negative point count");
+    if (npts > 0 && !xyz) return fail(WF_E_ARG, "coordinates are NULL");
+    const uint64_t h = npts > 0 ? hash_points(npts, geom.ndim, xyz) : 0;
+    for (auto& c : pcache)
+        if (c.ps && c.key == h && c.ps->npts == npts && c.coords.size() == (size_t)npts * geom.ndim &&
+            (npts == 0 || std::memcmp(c.coords.data(), xyz, c.coords.size() * sizeof(double)) == 0)) {
+            c.tick = ++tick;
+            *out = c.ps;
+            return WF_OK;
+        }
+    PointSet* ps = new (std::nothrow) PointSet();
+    if (!ps) return fail(WF_E_NOMEM, "host allocation");
+    wf_status st = ps->build(&geom, L, npts, xyz);
+    if (st != WF_OK) {
+        delete ps;
+        return st;
+    }
+    // evict the least recently used entry beyond the cache size (the device
+    // work that may still read it is drained first)
+    if (pcache.size() >= 16) {
+        size_t lru = 0;
+        for (size_t i = 1; i < pcache.size(); ++i)
+            if (pcache[i].tick < pcache[lru].tick) lru = i;
+        (void)hipDeviceSynchronize();
+        delete pcache[lru].ps;
+        pcache.erase(pcache.begin() + (long)lru);
+    }
+    PCache c;
+    c.key = h;
+    c.ps = ps;
+    c.tick = ++tick;
+    c.coords.assign(xyz, xyz + (size_t)npts * geom.ndim);
+    pcache.push_back(std::move(c));
+    *out = ps;
+    return WF_OK;
+}
+
+Model::~Model() {
+    (void)hipDeviceSynchronize();
+    for (auto& c : pcache) delete c.ps;
+}
+
+void Model::fill_step(StepParams& p, double dt) const {
+    std::memset(&p, 0, sizeof p);
+    p.kap = d_kap.f();
+    p.etax = d_etax.f();
+    p.etay = d_etay.f();
+    p.etaz = d_etaz.f();
+    p.nx = L.nx;
+    p.ny = L.ny;
+    p.nz = L.nz;
+    p.sx = L.sx;
+    p.sy = L.sy;
+    double inv = 0.0;
+    const double hx = geom.h[0], hz = geom.h[geom.ndim - 1];
+    const double hy = geom.ndim == 3 ? geom.h[1] : 1.0;
+    inv = 1.0 / (hx * hx) + 1.0 / (hz * hz) + (geom.ndim == 3 ? 1.0 / (hy * hy) : 0.0);
+    p.c0 = (float)(alpha[0] * inv);
+    for (int j = 1; j <= half; ++j) {
+        p.wx[j] = (float)(alpha[j] / (hx * hx));
+        p.wy[j] = geom.ndim == 3 ? (float)(alpha[j] / (hy * hy)) : 0.0f;
+        p.wz[j] = (float)(alpha[j] / (hz * hz));
+    }
+    p.inv2dt = (float)(1.0 / (2.0 * dt));
+    p.idt2 = (float)(1.0 / (dt * dt));
+    int cx = 0;
+    if (const char* s = std::getenv("WAVEFD_CX")) cx = std::atoi(s);
+    step_plan(p, geom.ndim, half, cx);
+}

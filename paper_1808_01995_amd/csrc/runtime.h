@@ -1,0 +1,134 @@
+// Internal host-side types of the propagator library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wavefd.h"
+#include "kernels.h"
+
+namespace wf {
+
+wf_status fail(wf_status code, const char* fmt, ...);
+const char* last_error();
+void clear_error();
+wf_status hip_check(hipError_t e, const char* what);
+
+void fd_weights(int half, double* alpha);
+double abs_weight_sum(int half);
+wf_status check_geom(const wf_geom* g);
+void comp_shape(const wf_geom* g, int64_t* nx, int64_t* ny, int64_t* nz);
+double critical_dt(const wf_geom* g, double vmax);
+std::vector<float> eta_profile(const wf_geom* g, int axis);
+
+// Owned device allocation.
+struct DevBuf {
+    void* ptr = nullptr;
+    int64_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void reset();
+    wf_status alloc(int64_t nbytes);
+    wf_status upload(const void* host, int64_t nbytes);   // synchronous
+    float* f() const { return static_cast<float*>(ptr); }
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Pitched field layout of a computational grid: element (x, y, z) at
+// x*sx + y*sy + z with sy >= nz a multiple of 4 (pad entries stay zero).
+struct Layout {
+    int ndim = 3;
+    int nx = 0, ny = 1, nz = 0;
+    int64_t sx = 0, sy = 0;
+    int64_t elems = 0;     // pitched size in floats
+    int64_t npoints = 0;   // nx*ny*nz
+    void init(const wf_geom* g);
+    int64_t field_bytes() const { return elems * 4 + 256; }
+};
+
+// Sparse points of one acquisition: a gather table for sampling and a
+// node-grouped table for deterministic injection.
+struct PointSet {
+    int npts = 0, K = 0, nnodes = 0;
+    DevBuf d_off, d_w;                          // [npts*K]
+    DevBuf d_noff, d_neta, d_seg, d_ept, d_ew;  // injection by node
+    wf_status build(const wf_geom* g, const Layout& L, int npts, const double* xyz);
+};
+
+}  // namespace wf
+
+struct PCache {
+    uint64_t key = 0;
+    wf::PointSet* ps = nullptr;
+    uint64_t tick = 0;
+    std::vector<double> coords;
+};
+
+struct wf_model {
+    virtual ~wf_model() = default;
+};
+
+struct Model : public wf_model {
+    wf_geom geom{};
+    int half = 0;
+    wf::Layout L;
+    double alpha[wf::kMaxHalf + 1]{};
+    wf::DevBuf d_m, d_kap, d_u[2], d_etax, d_etay, d_etaz, d_scratch;
+    float m_min = 0.f, m_max = 0.f;
+    double kap_dt = -1.0;
+    std::vector<PCache> pcache;
+    uint64_t tick = 0;
+
+    ~Model() override;
+    wf_status init(const wf_geom* g, const float* m_dev, hipStream_t s);
+    wf_status set_m(const float* m_dev, hipStream_t s);
+    wf_status ensure_kap(double dt, hipStream_t s);
+    wf_status check_dt(double dt) const;
+    double vmax() const;
+    wf_status points(int npts, const double* xyz, const wf::PointSet** out);
+    void fill_step(wf::StepParams& p, double dt) const;
+    int64_t bytes() const {
+        return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_etax.bytes + d_etay.bytes +
+               d_etaz.bytes + d_scratch.bytes;
+    }
+};
+
+namespace wf {
+
+// Kernel timing: while enabled, launches of `kind` are bracketed by events.
+struct ProfScope {
+    int kind;
+    hipStream_t s;
+    int slot = -1;
+    ProfScope(int kind, hipStream_t s);
+    ~ProfScope();
+};
+
+// Time loops (propagate.cpp).
+wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                      const PointSet& rec, float* rec_out, float* u_save, int save_every,
+                      hipStream_t s);
+wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const float* rec_in,
+                      const PointSet& src, float* src_out, hipStream_t s);
+wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                       const PointSet& rec, const float* residual, float* grad_out, int n_ck,
+                       int64_t budget, hipStream_t s);
+
+// Revolve schedule (revolve.cpp).
+int64_t revolve_cost(int64_t steps, int snaps);
+struct RevolveAction {
+    // ADVANCE: forward from state `at` to state `arg`; TAKESHOT: pin the current
+    // state (x_at) in slot `arg`; RESTORE: make slot `arg` (x_at) current;
+    // REVERSE: the adjoint of step `at` (needs x_at current); FREE: release slot.
+    enum Kind { ADVANCE, TAKESHOT, RESTORE, REVERSE, FREE } kind;
+    int64_t at;
+    int64_t arg;
+};
+wf_status revolve_schedule(int64_t steps, int snaps, std::vector<RevolveAction>& out);
+
+}  // namespace wf

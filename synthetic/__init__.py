@@ -125,7 +125,7 @@ def band_limited_noise(nt: int, ntr: int, dt: float, f0_hz: float, seed: int) ->
     w = (1.0 - 2.0 * a) * np.exp(-a)
     out = np.empty_like(noise)
     for r in range(ntr):
-        out[:, r] = np.convolve(noise[:, r], w, mode="same")
+        out[:, r] = np.convolve(noise[:, r], w, mode="full")[half:half + nt]
     return out
 
 

@@ -1,0 +1,149 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, element by element over whole shot records.
+
+Tolerances: receiver traces rel. L2 <= 1e-4, gradients rel. L2 <= 1e-3, GPU
+dot test <= 1e-4 (the FP32 bars of the specification). Sizes span several
+(y, z) tiles and x chunks with ragged tails; every space order 4..16 runs.
+"""
+import numpy as np
+import pytest
+
+from _harness import make_problem, noise, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu_forward(P, prop=None, save_every=None):
+    prop = prop or P.propagator()
+    out = prop.forward(P.dt, P.nt, P.src_xyz, torch.from_numpy(P.q32).cuda(), P.rec_xyz,
+                       save_every=save_every)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_c1_2d_so4_full_config():
+    """101 x 101, h = 10 m, v = 1.5 km/s, order 4, 500 steps, nbl 20, Ricker
+    10 Hz at the centre, 101 receivers at 20 m depth."""
+    from synthetic import config
+    import oracle
+    c = config("c1_2d")
+    from _harness import Problem
+    v = c.velocity()
+    m32 = (1.0 / oracle.pad_edge(v, c.nbl) ** 2).astype(np.float32)
+    dt = c.dt_factor * oracle.critical_dt(2, c.spacing, c.space_order, float(v.max()))
+    from synthetic import ricker
+    q = ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)
+    P = Problem(c.shape, c.spacing, c.nbl, c.space_order, c.nt, dt, float(v.max()), v, m32,
+                c.src, c.rec, q)
+    d_ref = P.oracle_forward()
+    d = _gpu_forward(P).cpu().numpy()
+    err = rel_l2(d, d_ref)
+    print("C1 rel L2 =", err)
+    assert err <= 1e-4
+    assert np.all(d[0] == 0)
+
+
+@pytest.mark.parametrize("k", [4, 6, 8, 10, 12, 14, 16])
+def test_2d_all_orders(k):
+    P = make_problem((53, 47), 9, k, 120, seed=k)
+    d = _gpu_forward(P).cpu().numpy()
+    assert rel_l2(d, P.oracle_forward()) <= 1e-4
+
+
+@pytest.mark.parametrize("k", [4, 8, 12, 16])
+def test_3d_orders_ragged_tiles(k):
+    """(y, z) tiles of 16 x 64 and x chunks: 71 x 37 x 93 computational nodes
+    leave ragged tiles on every axis."""
+    P = make_problem((55, 21, 77), 8, k, 90, seed=10 + k, nrec=60)
+    d = _gpu_forward(P).cpu().numpy()
+    err = rel_l2(d, P.oracle_forward())
+    print("3D k=%d rel L2 = %.3g" % (k, err))
+    assert err <= 1e-4
+
+
+def test_3d_so8_two_layer_and_save():
+    P = make_problem((40, 36, 44), 10, 8, 80, seed=3, kind="two_layer", nrec=50)
+    d, u = _gpu_forward(P, save_every=20)
+    d_ref, u_ref = P.oracle_forward(save=True)
+    assert rel_l2(d.cpu().numpy(), d_ref) <= 1e-4
+    u = u.cpu().numpy()
+    for i, n in enumerate(range(0, P.nt, 20)):
+        if n == 0:
+            assert np.all(u[i] == 0)
+        else:
+            assert rel_l2(u[i], u_ref[n]) <= 1e-4
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_adjoint_parity_and_dot_test(ndim):
+    shape = (48, 41) if ndim == 2 else (30, 26, 34)
+    P = make_problem(shape, 8, 8, 100, seed=20 + ndim, nsrc=3, nrec=40)
+    prop = P.propagator()
+    x = noise(P.nt, 3, P.dt, 20.0, seed=1).astype(np.float32)
+    y = noise(P.nt, 40, P.dt, 20.0, seed=2).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.from_numpy(y).cuda()
+    Fx = prop.forward(P.dt, P.nt, P.src_xyz, xt, P.rec_xyz).cpu().numpy().astype(np.float64)
+    FTy = prop.adjoint(P.dt, P.nt, P.rec_xyz, yt, P.src_xyz).cpu().numpy().astype(np.float64)
+    # against the oracle's adjoint on the same y
+    FTy_ref = P.oracle_adjoint(y.astype(np.float64))
+    assert rel_l2(FTy, FTy_ref) <= 1e-4
+    assert np.all(FTy[-1] == 0)
+    lhs = float(np.sum(Fx * y))
+    rhs = float(np.sum(x * FTy))
+    rel = abs(lhs - rhs) / abs(lhs)
+    print("GPU dot test", ndim, "D:", lhs, rhs, rel)
+    assert rel <= 1e-4
+
+
+def test_deterministic_bitwise():
+    P = make_problem((40, 35, 50), 8, 8, 60, seed=7, nsrc=2)
+    prop = P.propagator()
+    a = _gpu_forward(P, prop).cpu().numpy()
+    b = _gpu_forward(P, prop).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases():
+    """nt = 1, no receivers, no sources, sources on the last node and in the
+    layer, nz not a multiple of 4."""
+    P = make_problem((23, 19), 5, 4, 40, seed=4)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    d1 = prop.forward(P.dt, 1, P.src_xyz, q[:1].contiguous(), P.rec_xyz)
+    torch.cuda.synchronize()
+    assert d1.shape == (1, P.rec_xyz.shape[0]) and torch.all(d1 == 0)
+    d0 = prop.forward(P.dt, P.nt, np.zeros((0, 2)), torch.zeros((P.nt, 0), device="cuda"), P.rec_xyz)
+    assert torch.all(d0 == 0)
+    prop.forward(P.dt, P.nt, P.src_xyz, q, np.zeros((0, 2)))
+    # source exactly on the last node of the computational grid and one in the layer
+    ext = [(n - 1 + P.nbl) * h for n, h in zip(P.shape_phys, P.spacing)]
+    src = np.array([ext, [-P.nbl * P.spacing[0] * 0.5, 33.3]])
+    q2 = np.tile(P.q32[:, :1], (1, 2))
+    import oracle
+    d = prop.forward(P.dt, P.nt, src, torch.from_numpy(q2).cuda(), P.rec_xyz).cpu().numpy()
+    d_ref = oracle.forward(P.grid(), P.m64(), P.eta(), P.dt, P.nt, P.pts(src), q2.astype(np.float64),
+                           P.pts(P.rec_xyz))
+    assert rel_l2(d, d_ref) <= 1e-4
+
+
+def test_host_side_rejections():
+    """CFL, domain and shape errors are reported before any work is queued."""
+    from paper_1808_01995_amd import WaveFDError, _abi
+    P = make_problem((20, 22), 4, 8, 10, seed=5)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    dcrit = prop.critical_dt()
+    with pytest.raises(WaveFDError) as e:
+        prop.forward(dcrit * 1.01, P.nt, P.src_xyz, q, P.rec_xyz)
+    assert e.value.status == _abi.WF_E_CFL
+    with pytest.raises(WaveFDError) as e:
+        prop.forward(P.dt, P.nt, np.array([[-1000.0, 50.0]]), q, P.rec_xyz)
+    assert e.value.status == _abi.WF_E_DOMAIN
+    bad = P.m32.copy()
+    bad[3, 3] = -1.0
+    with pytest.raises(WaveFDError) as e:
+        P.propagator(bad)
+    assert e.value.status == _abi.WF_E_ARG
