@@ -92,6 +92,8 @@ def _load():
         "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
         "wf_gradient": (I, [P, D, I, I, P, P, I, P, P, P, I, I64, P]),
         "wf_revolve_forward_steps": (I64, [I64, I]),
+        "wf_profile_enable": (I, [I]),
+        "wf_profile_read": (I, [I, P, P, I]),
         "wf_engine_create": (I, [I64, I, P]),
         "wf_engine_submit": (I, [P, ctypes.POINTER(wf_request), P]),
         "wf_engine_poll": (I, [P, P, P, I, P, I]),
@@ -110,7 +112,8 @@ lib = _load()
 # every symbol declared in include/wavefd.h
 EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
            "wf_model_set_m", "wf_model_bytes", "wf_model_destroy", "wf_forward", "wf_adjoint",
-           "wf_gradient", "wf_revolve_forward_steps", "wf_engine_create", "wf_engine_submit",
+           "wf_gradient", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
+           "wf_engine_create", "wf_engine_submit",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
 
 
@@ -237,6 +240,23 @@ def wf_gradient(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, residual, 
 
 def wf_revolve_forward_steps(steps: int, snaps: int) -> int:
     return int(lib.wf_revolve_forward_steps(int(steps), int(snaps)))
+
+
+WF_KERNEL_STEP = 0
+WF_KERNEL_INJECT = 1
+WF_KERNEL_SAMPLE = 2
+
+
+def wf_profile_enable(on: bool):
+    _check(lib.wf_profile_enable(1 if on else 0))
+
+
+def wf_profile_read(kind: int, reset: bool = False):
+    """(summed device ms, launch count) of kernel `kind` since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib.wf_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
 
 
 def wf_engine_create(hbm_budget_bytes: int, max_slots: int):

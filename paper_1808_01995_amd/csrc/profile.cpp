@@ -61,23 +61,24 @@ ProfScope::ProfScope(int k, hipStream_t st) : kind(k), s(st) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     if (g_recs.size() > 4096) drain(false);
-    hipEvent_t a = get_event(), b = get_event();
-    if (!a || !b) return;
-    if (hipEventRecord(a, s) != hipSuccess) return;
-    g_recs.push_back({kind, a, b});
-    slot = (int)g_recs.size() - 1;
+    a = get_event();
+    b = get_event();
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+        if (a) g_free.push_back(a);
+        if (b) g_free.push_back(b);
+        a = b = nullptr;
+    }
 }
 
 ProfScope::~ProfScope() {
-    if (slot < 0) return;
+    if (!a) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    // find our record (drain() may have compacted the vector meanwhile only for
-    // finished records, and ours has no stop event recorded yet)
-    for (size_t i = g_recs.size(); i-- > 0;)
-        if (g_recs[i].kind == kind && (int)i <= slot) {
-            (void)hipEventRecord(g_recs[i].b, s);
-            return;
-        }
+    if (hipEventRecord(b, s) == hipSuccess) {
+        g_recs.push_back({kind, a, b});
+    } else {
+        g_free.push_back(a);
+        g_free.push_back(b);
+    }
 }
 
 }  // namespace wf

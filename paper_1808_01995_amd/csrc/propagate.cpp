@@ -37,6 +37,7 @@ wf_status step(StepParams& p, const Model& md, const float* cur, const float* ol
     p.out = out;
     p.grad = grad;
     p.ufwd = ufwd;
+    ProfScope prof(WF_KERNEL_STEP, s);
     return hip_check(launch_step(p, md.geom.ndim, md.half, img, s), "stencil launch");
 }
 
@@ -57,11 +58,13 @@ wf_status inject(const Model& md, const PointSet& ps, const float* vals, float* 
     ip.nnodes = ps.nnodes;
     ip.inv2dt = sp.inv2dt;
     ip.idt2 = sp.idt2;
+    ProfScope prof(WF_KERNEL_INJECT, s);
     return hip_check(launch_inject(ip, s), "inject launch");
 }
 
 wf_status sample(const PointSet& ps, const float* field, float* out, hipStream_t s) {
     if (ps.npts == 0) return WF_OK;
+    ProfScope prof(WF_KERNEL_SAMPLE, s);
     return hip_check(launch_sample(field, ps.d_off.as<int64_t>(), ps.d_w.f(), ps.npts, ps.K, out, s),
                      "sample launch");
 }

@@ -104,7 +104,7 @@ namespace wf {
 struct ProfScope {
     int kind;
     hipStream_t s;
-    int slot = -1;
+    hipEvent_t a = nullptr, b = nullptr;
     ProfScope(int kind, hipStream_t s);
     ~ProfScope();
 };

@@ -1,0 +1,131 @@
+"""GPU gradient (adjoint-state, eqs. AS, Grad, Adj): parity with the FP64
+oracle (rel. L2 <= 1e-3), bitwise equality across checkpoint counts (store-all
+and revolve with several snapshot counts), a Taylor test of the GPU objective,
+and the torch.autograd path."""
+import numpy as np
+import pytest
+
+import oracle
+from _harness import Problem, make_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _anomaly_problem(n=36, nbl=8, k=8, steps=150, ndim=3):
+    """Reduced gradient workload: 2.0 km/s background with a Gaussian 2.5 km/s
+    anomaly; true and initial models share dt (from v_max = 2.5)."""
+    from synthetic import gaussian_anomaly_velocity, ricker, grid_receivers, line_receivers
+    shape = (n,) * ndim
+    h = (10.0,) * ndim
+    v_true = gaussian_anomaly_velocity(shape, radius_cells=n * 0.15)
+    v0 = np.full(shape, 2.0)
+    ext = (n - 1) * 10.0
+    dt = 0.5 * oracle.critical_dt(ndim, h, k, 2.5)
+    nt = steps + 1
+    q = ricker(nt, dt, 25.0)[:, None].astype(np.float32)
+    if ndim == 3:
+        src = np.array([[ext / 2, ext / 2, 20.0]])
+        rec = grid_receivers(8, 8, ext, ext, 20.0)
+    else:
+        src = np.array([[ext / 2, 20.0]])
+        rec = line_receivers(n, 0.0, ext, 20.0)
+    m_true = (1.0 / oracle.pad_edge(v_true, nbl) ** 2).astype(np.float32)
+    m0 = (1.0 / oracle.pad_edge(v0, nbl) ** 2).astype(np.float32)
+    P = Problem(shape, h, nbl, k, nt, dt, 2.5, v0, m0, src, rec, q)
+    P_true = Problem(shape, h, nbl, k, nt, dt, 2.5, v_true, m_true, src, rec, q)
+    return P, P_true
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_gradient_parity_with_oracle(ndim):
+    P, Pt = _anomaly_problem(ndim=ndim, n=36 if ndim == 3 else 90, steps=150 if ndim == 3 else 300)
+    d_obs = Pt.oracle_forward()
+    d0 = P.oracle_forward()
+    res32 = (d0 - d_obs).astype(np.float32)
+    g_ref = P.oracle_gradient(res32.astype(np.float64))
+    prop = P.propagator()
+    g = prop.gradient(P.dt, P.nt, P.src_xyz, torch.from_numpy(P.q32).cuda(), P.rec_xyz,
+                      torch.from_numpy(res32).cuda(), n_checkpoints=5).cpu().numpy()
+    err = rel_l2(g, g_ref)
+    print("gradient %dD rel L2 = %.3g" % (ndim, err))
+    assert err <= 1e-3
+
+
+def test_gradient_bitwise_across_checkpoint_counts():
+    P, Pt = _anomaly_problem(n=30, steps=97)
+    d_obs = Pt.oracle_forward()
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    d = prop.forward(P.dt, P.nt, P.src_xyz, q, P.rec_xyz)
+    r = (d - torch.from_numpy(d_obs.astype(np.float32)).cuda()).contiguous()
+    ref = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    for s in (1, 2, 3, 7, 20, 96, 500, 0):
+        g = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=s)
+        assert torch.equal(g, ref), s
+    assert torch.isfinite(ref).all() and ref.abs().max() > 0
+
+
+def test_gradient_budget_rejection_and_auto():
+    from paper_1808_01995_amd import WaveFDError, _abi
+    P, Pt = _anomaly_problem(n=20, steps=40)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    r = torch.ones((P.nt, P.rec_xyz.shape[0]), device="cuda")
+    with pytest.raises(WaveFDError) as e:
+        prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=3, hbm_budget_bytes=1000)
+    assert e.value.status == _abi.WF_E_BUDGET
+    fb = prop.npoints * 4
+    g_small = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=0,
+                            hbm_budget_bytes=int(14 * fb))
+    g_all = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    assert torch.equal(g_small, g_all)
+
+
+def test_gpu_taylor():
+    """Taylor test of the GPU objective with the GPU gradient (FP32): eps0 is
+    first order and eps1 second order in h over the range FP32 resolves."""
+    P, Pt = _anomaly_problem(n=28, steps=120)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    d_obs = torch.from_numpy(Pt.oracle_forward().astype(np.float32)).cuda()
+    m0 = torch.from_numpy(P.m32).cuda()
+    dm = torch.from_numpy(Pt.m32).cuda() - m0
+
+    def phi(m):
+        prop.set_m(m.contiguous())
+        d = prop.forward(P.dt, P.nt, P.src_xyz, q, P.rec_xyz)
+        return 0.5 * float(((d - d_obs).double() ** 2).sum()), d
+
+    f0, d = phi(m0)
+    g = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, (d - d_obs).contiguous(), n_checkpoints=4)
+    gdm = float((g.double() * dm.double()).sum())
+    hs = 2.0 ** -np.arange(1, 6)
+    e0, e1 = [], []
+    for hh in hs:
+        f, _ = phi(m0 + hh * dm)
+        e0.append(abs(f - f0))
+        e1.append(abs(f - f0 - hh * gdm))
+    s0 = np.polyfit(np.log(hs), np.log(e0), 1)[0]
+    s1 = np.polyfit(np.log(hs), np.log(e1), 1)[0]
+    print("GPU Taylor slopes", s0, s1)
+    assert 0.85 < s0 < 1.2 and 1.7 < s1 < 2.4
+
+
+def test_autograd_function_matches_gradient():
+    from paper_1808_01995_amd import model_data, pad_replicate
+    P, Pt = _anomaly_problem(n=24, steps=80, ndim=2)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    d_obs = torch.from_numpy(Pt.oracle_forward().astype(np.float32)).cuda()
+    m_phys = torch.full(P.shape_phys, 1.0 / 4.0, device="cuda", requires_grad=True)
+    m_comp = pad_replicate(m_phys, P.nbl)
+    d = model_data(m_comp, prop, P.dt, P.nt, P.src_xyz, q, P.rec_xyz, 3)
+    loss = 0.5 * ((d - d_obs) ** 2).sum()
+    loss.backward()
+    # reference: J^T r on the computational grid, folded onto the physical grid
+    r = (d.detach() - d_obs).contiguous()
+    g_comp = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    m2 = torch.zeros(P.shape_phys, device="cuda", dtype=torch.float64, requires_grad=True)
+    (pad_replicate(m2, P.nbl) * g_comp.double()).sum().backward()
+    assert rel_l2(m_phys.grad.double().cpu().numpy(), m2.grad.cpu().numpy()) < 1e-5

@@ -147,3 +147,32 @@ def test_host_side_rejections():
     with pytest.raises(WaveFDError) as e:
         P.propagator(bad)
     assert e.value.status == _abi.WF_E_ARG
+
+
+def test_c2_full_size_against_stored_oracle_record():
+    """The 3D order-8 workload at full size (336^3 computational, 1000 updates,
+    the launch configuration the benchmark times) against the FP64 oracle's
+    record at every 8th receiver in x and y (written by
+    tests/golden/make_golden.py, which calls only the oracle)."""
+    import os
+    from synthetic import config, ricker
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_so8_record_sampled.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle record not generated")
+    gold = np.load(path)
+    c = config("c2_3d_so8")
+    v = c.velocity()
+    import oracle
+    m32 = (1.0 / oracle.pad_edge(v, c.nbl) ** 2).astype(np.float32)
+    dt = float(gold["dt"])
+    assert abs(dt - c.dt_factor * oracle.critical_dt(3, c.spacing, 8, float(v.max()))) < 1e-15
+    from paper_1808_01995_amd import Propagator
+    prop = Propagator(m=torch.from_numpy(m32).cuda(), shape=c.shape, spacing=c.spacing, nbl=c.nbl,
+                      space_order=8, c_ref=float(v.max()))
+    q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    d = prop.forward(dt, c.nt, c.src, q, c.rec).cpu().numpy()
+    sel = gold["receiver_index"]
+    err = rel_l2(d[:, sel], gold["record"])
+    print("C2 full-size sampled record rel L2 = %.3g" % err)
+    assert err <= 1e-4
+    prop.close()
