@@ -17,7 +17,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwavefd.so")
+# WAVEFD_LIBRARY selects another build of the same library (tuning runs).
+LIB_PATH = os.environ.get("WAVEFD_LIBRARY") or os.path.join(HERE, "libwavefd.so")
 
 WF_OK = 0
 WF_E_ARG = -1

@@ -10,10 +10,16 @@ namespace wf {
 
 constexpr int kMaxHalf = 8;   // space order up to 16
 
+// Number of zero ghost x-planes kept before and after every field that the
+// step kernel reads (it needs M + prefetch distance <= 10 of them).
+constexpr int kGhostPlanes = 12;
+
 // Parameters of one time step of the fused update
 //   out = (2 cur - (1 - g) old + kap * Lap(cur)) / (1 + g),  g = eta kap / (2 dt)
 // on a pitched field layout: element (x, y, z) at x*sx + y*sy + z, sy = pitch
 // (a multiple of 4 floats, >= nz rounded up to 4; the pad is kept at zero).
+// cur, old, kap, ufwd and grad point at plane 0 of allocations that extend by
+// kGhostPlanes zero planes on both sides in x.
 // `out` may alias `old` (in-place update; every element of old is read by the
 // thread that then writes the same element of out).
 // With imaging on (adjoint sweeps of the gradient): grad -= ufwd * (out - 2 cur
@@ -36,16 +42,18 @@ struct StepParams {
     float wx[kMaxHalf + 1], wy[kMaxHalf + 1], wz[kMaxHalf + 1];  // alpha_j / h_a^2
     float inv2dt;
     float idt2;
+    int tile;            // host side: which compiled tile shape step_plan chose
 };
 
-// Tile shapes chosen by the launcher (threads along z carry 4 points each).
+// Tile shapes (threads along z carry 4 points each).
 struct TileShape {
     int bz, by;   // threads along z and y per block
 };
 
-TileShape step_tile(int ndim, int half);
-// Fill ntz/nty/nchunks/nblocks/cx for the given chunk length (0 = automatic).
-void step_plan(StepParams& p, int ndim, int half, int cx_request);
+TileShape step_tile(int ndim, int tile);
+// Choose the tile shape and the x-chunking (ntz/nty/nchunks/nblocks/cx); a
+// positive cx_request forces the chunk length, tile_request >= 0 the shape.
+void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request);
 hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s);
 
 // Sparse injection at unique nodes (deterministic, no atomics):

@@ -32,6 +32,31 @@ __device__ __forceinline__ void st4(float* p, const float4& v) {
     *reinterpret_cast<float4*>(p) = v;
 }
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+// Streams that are read or written exactly once per step (the old field,
+// kappa, the output) bypass L2 retention so that it keeps the current field,
+// whose rows are re-read as halos by the neighbouring tiles.
+#ifndef WF_STREAM_NT
+#define WF_STREAM_NT 1
+#endif
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4s(const float* p) {
+#if WF_STREAM_NT
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+#else
+    return *reinterpret_cast<const float4*>(p);
+#endif
+}
+__device__ __forceinline__ void st4s(float* p, const float4& v) {
+#if WF_STREAM_NT
+    f4v t;
+    t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+    __builtin_nontemporal_store(t, reinterpret_cast<f4v*>(p));
+#else
+    *reinterpret_cast<float4*>(p) = v;
+#endif
+}
 __device__ __forceinline__ float comp(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
@@ -56,17 +81,35 @@ __device__ __forceinline__ float update(float c, float old, float kap, float lap
 }
 
 // ---------------------------------------------------------------------------
-// 3D step. Block: BZ x BY threads, tile TZ = 4 BZ (z) by BY (y).
+// Time step, 2D ([x][z]) or 3D ([x][y][z]).
+//
+// Block: BZ x BY threads over a (y, z) tile of TZ = 4 BZ by BY nodes; each
+// thread owns 4 consecutive z nodes of one y row and walks its x range
+// [xb, xe). The 2M+1 x-neighbours of the thread's column live in a ring of
+// NQ = 2M + 1 + PF float4 registers; the x loop is unrolled by NQ so that the
+// ring rotates by renaming (no register moves) and plane x + M + PF is loaded
+// PF planes before it is first used. The old field, kappa and the y/z halos
+// of the next plane are loaded one plane ahead. The staged plane alternates
+// between two LDS buffers, so one barrier per plane suffices: a thread can
+// only overwrite a buffer after every thread has passed the barrier of the
+// plane in between.
 // ---------------------------------------------------------------------------
-template <int M, int BZ, int BY, bool IMG>
-__global__ void __launch_bounds__(BZ * BY) k_step3d(const StepParams p) {
+template <bool D3, int M, int BZ, int BY, int PF, bool IMG>
+__global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
     constexpr int NT = BZ * BY;
     constexpr int TZ = 4 * BZ;
     constexpr int P = (M + 3) & ~3;     // z halo rounded up to whole float4s
     constexpr int HZ = P / 4;
     constexpr int LW = TZ + 2 * P;      // LDS row (floats)
-    constexpr int LH = BY + 2 * M;      // LDS rows
-    __shared__ __attribute__((aligned(16))) float lds[LH * LW];
+    constexpr int MY = D3 ? M : 0;      // y halo rows
+    constexpr int LH = BY + 2 * MY;     // LDS rows per buffer
+    constexpr int LBUF = LH * LW;
+    constexpr int NQ = 2 * M + 1 + PF;
+    constexpr int NHY = 2 * MY * BZ;    // y-halo float4 loads per plane
+    constexpr int NHZ = 2 * BY * HZ;    // z-halo float4 loads per plane
+    constexpr int JY = NHY > 0 ? (NHY + NT - 1) / NT : 1;
+    constexpr int JZ = (NHZ + NT - 1) / NT;
+    __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];
 
     const int r = xcd_remap(blockIdx.x, p.nblocks);
     if (r >= p.nblocks) return;
@@ -83,227 +126,164 @@ __global__ void __launch_bounds__(BZ * BY) k_step3d(const StepParams p) {
     const bool own = (y < p.ny) && (z < p.nz);
     const int xb = ich * p.cx;
     const int xe = min(xb + p.cx, p.nx);
+    const int64_t sx = p.sx;
+    // Loads are unconditional (a predicated load feeds a register merge that
+    // would force the pipeline to drain): threads outside the grid read column
+    // 0 and are masked where their values could reach a neighbour; x planes
+    // beyond the grid are the zero ghost planes of the field allocation.
     const int64_t col = own ? (int64_t)y * p.sy + z : 0;
 
-    float eyz[4];
+    // halo jobs of this thread (the same for every plane)
+    int hy_l[JY], hz_l[JZ];
+    int64_t hy_c[JY], hz_c[JZ];
+    bool hy_v[JY], hz_v[JZ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        eyz[i] = (own && z + i < p.nz) ? (p.etay[y] + p.etaz[z + i]) : 0.0f;
-
-    float4 q[2 * M + 1];
-#pragma unroll
-    for (int j = 0; j < 2 * M; ++j) {
-        const int xx = xb - M + j;
-        q[j] = (own && xx >= 0 && xx < p.nx) ? ld4(p.cur + (int64_t)xx * p.sx + col) : zero4();
-    }
-    float* lrow = lds + (ly + M) * LW;
-
-    for (int x = xb; x < xe; ++x) {
-        const int64_t base = (int64_t)x * p.sx;
-        {
-            const int xn = x + M;
-            q[2 * M] = (own && xn < p.nx) ? ld4(p.cur + (int64_t)xn * p.sx + col) : zero4();
-        }
-        const float4 uo = own ? ld4(p.old + base + col) : zero4();
-        const float4 kp = own ? ld4(p.kap + base + col) : zero4();
-        float4 uf = zero4(), gr = zero4();
-        if (IMG && own) {
-            uf = ld4(p.ufwd + base + col);
-            gr = ld4(p.grad + base + col);
-        }
-        const float ex = p.etax[x];
-
-        // stage the plane: own centre, y halo rows, z halo columns
-        st4(lrow + P + 4 * lz, q[M]);
-        for (int i = tid; i < 2 * M * BZ; i += NT) {
+    for (int j = 0; j < JY; ++j) {
+        const int i = tid + j * NT;
+        hy_l[j] = -1;
+        hy_v[j] = false;
+        hy_c[j] = 0;
+        if (i < NHY) {
             const int rr = i / BZ, cz = i - rr * BZ;
-            const int lr = rr < M ? rr : rr + BY;
-            const int gy = y0 - M + lr;
+            const int lr = rr < MY ? rr : rr + BY;
+            const int gy = y0 - MY + lr;
             const int gz = z0 + 4 * cz;
-            float4 v = zero4();
-            if (gy >= 0 && gy < p.ny && gz < p.nz) v = ld4(p.cur + base + (int64_t)gy * p.sy + gz);
-            st4(lds + lr * LW + P + 4 * cz, v);
+            hy_l[j] = lr * LW + P + 4 * cz;
+            hy_v[j] = gy >= 0 && gy < p.ny && gz < p.nz;
+            hy_c[j] = hy_v[j] ? (int64_t)gy * p.sy + gz : 0;
         }
-        for (int i = tid; i < 2 * BY * HZ; i += NT) {
+    }
+#pragma unroll
+    for (int j = 0; j < JZ; ++j) {
+        const int i = tid + j * NT;
+        hz_l[j] = -1;
+        hz_v[j] = false;
+        hz_c[j] = 0;
+        if (i < NHZ) {
             const int rr = i / (2 * HZ), k = i - rr * (2 * HZ);
             const int side = k / HZ, kk = k - side * HZ;
             const int lc = side ? (P + TZ + 4 * kk) : 4 * kk;
             const int gz = z0 - P + lc;
             const int gy = y0 + rr;
-            float4 v = zero4();
-            if (gy < p.ny && gz >= 0 && gz < p.nz) v = ld4(p.cur + base + (int64_t)gy * p.sy + gz);
-            st4(lds + (rr + M) * LW + lc, v);
+            hz_l[j] = (rr + MY) * LW + lc;
+            hz_v[j] = gy < p.ny && gz >= 0 && gz < p.nz;
+            hz_c[j] = hz_v[j] ? (int64_t)gy * p.sy + gz : 0;
         }
-        __syncthreads();
+    }
 
-        float lap[4];
-        {
-            const float4 c = q[M];
+    float eyz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        eyz[i] = (own && z + i < p.nz) ? ((D3 ? p.etay[y] : 0.0f) + p.etaz[z + i]) : 0.0f;
+
+    float4 ring[NQ];
+#pragma unroll
+    for (int s = 0; s < 2 * M + PF; ++s) ring[s] = ld4(p.cur + (int64_t)(xb - M + s) * sx + col);
+    ring[NQ - 1] = zero4();
+
+    float4 uo_n, kp_n, uf_n = zero4(), gr_n = zero4();
+    float4 hy_n[JY], hz_n[JZ];
+    float ex_n;
+    auto load_next = [&](int xx) {
+        const int64_t b = (int64_t)xx * sx;
+        ex_n = p.etax[min(xx, p.nx - 1)];
+        uo_n = ld4s(p.old + b + col);
+        kp_n = ld4s(p.kap + b + col);
+        if (IMG) {
+            uf_n = ld4s(p.ufwd + b + col);
+            gr_n = ld4s(p.grad + b + col);
+        }
+#pragma unroll
+        for (int j = 0; j < JY; ++j) hy_n[j] = ld4(p.cur + b + hy_c[j]);
+#pragma unroll
+        for (int j = 0; j < JZ; ++j) hz_n[j] = ld4(p.cur + b + hz_c[j]);
+    };
+    load_next(xb);
+
+    for (int xg = xb; xg < xe; xg += NQ) {
+#pragma unroll
+        for (int ph = 0; ph < NQ; ++ph) {
+            const int x = xg + ph;
+            if (x >= xe) break;
+            // this plane's operands, loaded one plane ago
+            const float4 uo = uo_n, kp = kp_n, uf = uf_n, gr = gr_n;
+            const float ex = ex_n;
+            float4 hy[JY], hz[JZ];
+#pragma unroll
+            for (int j = 0; j < JY; ++j) hy[j] = hy_n[j];
+#pragma unroll
+            for (int j = 0; j < JZ; ++j) hz[j] = hz_n[j];
+            load_next(x + 1);   // plane nx at the end is a ghost plane
+            ring[(ph + 2 * M + PF) % NQ] = ld4(p.cur + (int64_t)(x + M + PF) * sx + col);
+            const float4 c = ring[(ph + M) % NQ];
+            float* L = lds + (x & 1) * LBUF;
+            float* lrow = L + (ly + MY) * LW;
+            st4(lrow + P + 4 * lz, own ? c : zero4());
+#pragma unroll
+            for (int j = 0; j < JY; ++j)
+                if (hy_l[j] >= 0) st4(L + hy_l[j], hy_v[j] ? hy[j] : zero4());
+#pragma unroll
+            for (int j = 0; j < JZ; ++j)
+                if (hz_l[j] >= 0) st4(L + hz_l[j], hz_v[j] ? hz[j] : zero4());
+            __syncthreads();
+
+            float lap[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) lap[i] = p.c0 * comp(c, i);
 #pragma unroll
             for (int j = 1; j <= M; ++j) {
-                const float4 a = q[M - j], b = q[M + j];
+                const float4 a = ring[(ph + M - j) % NQ], b = ring[(ph + M + j) % NQ];
                 lap[0] = fmaf(p.wx[j], a.x + b.x, lap[0]);
                 lap[1] = fmaf(p.wx[j], a.y + b.y, lap[1]);
                 lap[2] = fmaf(p.wx[j], a.z + b.z, lap[2]);
                 lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
             }
+            if (D3) {
 #pragma unroll
-            for (int j = 1; j <= M; ++j) {
-                const float4 a = ld4(lds + (ly + M - j) * LW + P + 4 * lz);
-                const float4 b = ld4(lds + (ly + M + j) * LW + P + 4 * lz);
-                lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
-                lap[1] = fmaf(p.wy[j], a.y + b.y, lap[1]);
-                lap[2] = fmaf(p.wy[j], a.z + b.z, lap[2]);
-                lap[3] = fmaf(p.wy[j], a.w + b.w, lap[3]);
-            }
-            float w[2 * P + 4];
-#pragma unroll
-            for (int k = 0; k < (2 * P + 4) / 4; ++k) {
-                const float4 v = ld4(lrow + 4 * lz + 4 * k);
-                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 1; j <= M; ++j)
-                    lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
-        }
-
-        float4 o;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float v = update(comp(q[M], i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], p.inv2dt);
-            if (z + i >= p.nz) v = 0.0f;
-            set_comp(o, i, v);
-        }
-        if (own) {
-            st4(p.out + base + col, o);
-            if (IMG) {
-                float4 g2;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float lapt = comp(o, i) - 2.0f * comp(q[M], i) + comp(uo, i);
-                    set_comp(g2, i, comp(gr, i) - comp(uf, i) * lapt * p.idt2);
+                for (int j = 1; j <= MY; ++j) {
+                    const float4 a = ld4(lrow - j * LW + P + 4 * lz);
+                    const float4 b = ld4(lrow + j * LW + P + 4 * lz);
+                    lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
+                    lap[1] = fmaf(p.wy[j], a.y + b.y, lap[1]);
+                    lap[2] = fmaf(p.wy[j], a.z + b.z, lap[2]);
+                    lap[3] = fmaf(p.wy[j], a.w + b.w, lap[3]);
                 }
-                st4(p.grad + base + col, g2);
             }
-        }
-        __syncthreads();
+            {
+                float w[2 * P + 4];
 #pragma unroll
-        for (int j = 0; j < 2 * M; ++j) q[j] = q[j + 1];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// 2D step ([x][z]). Block: BZ threads, tile of TZ = 4 BZ z points, streaming x.
-// ---------------------------------------------------------------------------
-template <int M, int BZ, bool IMG>
-__global__ void __launch_bounds__(BZ) k_step2d(const StepParams p) {
-    constexpr int TZ = 4 * BZ;
-    constexpr int P = (M + 3) & ~3;
-    constexpr int HZ = P / 4;
-    constexpr int LW = TZ + 2 * P;
-    __shared__ __attribute__((aligned(16))) float lds[LW];
-
-    const int r = xcd_remap(blockIdx.x, p.nblocks);
-    if (r >= p.nblocks) return;
-    const int itz = r % p.ntz;
-    const int ich = r / p.ntz;
-    const int tid = threadIdx.x;
-    const int z0 = itz * TZ;
-    const int z = z0 + 4 * tid;
-    const bool own = z < p.nz;
-    const int xb = ich * p.cx;
-    const int xe = min(xb + p.cx, p.nx);
-    const int64_t col = own ? z : 0;
-
-    float ez[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ez[i] = (own && z + i < p.nz) ? p.etaz[z + i] : 0.0f;
-
-    float4 q[2 * M + 1];
-#pragma unroll
-    for (int j = 0; j < 2 * M; ++j) {
-        const int xx = xb - M + j;
-        q[j] = (own && xx >= 0 && xx < p.nx) ? ld4(p.cur + (int64_t)xx * p.sx + col) : zero4();
-    }
-
-    for (int x = xb; x < xe; ++x) {
-        const int64_t base = (int64_t)x * p.sx;
-        {
-            const int xn = x + M;
-            q[2 * M] = (own && xn < p.nx) ? ld4(p.cur + (int64_t)xn * p.sx + col) : zero4();
-        }
-        const float4 uo = own ? ld4(p.old + base + col) : zero4();
-        const float4 kp = own ? ld4(p.kap + base + col) : zero4();
-        float4 uf = zero4(), gr = zero4();
-        if (IMG && own) {
-            uf = ld4(p.ufwd + base + col);
-            gr = ld4(p.grad + base + col);
-        }
-        const float ex = p.etax[x];
-
-        st4(lds + P + 4 * tid, q[M]);
-        for (int i = tid; i < 2 * HZ; i += BZ) {
-            const int side = i / HZ, kk = i - side * HZ;
-            const int lc = side ? (P + TZ + 4 * kk) : 4 * kk;
-            const int gz = z0 - P + lc;
-            float4 v = zero4();
-            if (gz >= 0 && gz < p.nz) v = ld4(p.cur + base + gz);
-            st4(lds + lc, v);
-        }
-        __syncthreads();
-
-        float lap[4];
-        {
-            const float4 c = q[M];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) lap[i] = p.c0 * comp(c, i);
-#pragma unroll
-            for (int j = 1; j <= M; ++j) {
-                const float4 a = q[M - j], b = q[M + j];
-                lap[0] = fmaf(p.wx[j], a.x + b.x, lap[0]);
-                lap[1] = fmaf(p.wx[j], a.y + b.y, lap[1]);
-                lap[2] = fmaf(p.wx[j], a.z + b.z, lap[2]);
-                lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
-            }
-            float w[2 * P + 4];
-#pragma unroll
-            for (int k = 0; k < (2 * P + 4) / 4; ++k) {
-                const float4 v = ld4(lds + 4 * tid + 4 * k);
-                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 1; j <= M; ++j)
-                    lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
-        }
-
-        float4 o;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float v = update(comp(q[M], i), comp(uo, i), comp(kp, i), lap[i], ex + ez[i], p.inv2dt);
-            if (z + i >= p.nz) v = 0.0f;
-            set_comp(o, i, v);
-        }
-        if (own) {
-            st4(p.out + base + col, o);
-            if (IMG) {
-                float4 g2;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float lapt = comp(o, i) - 2.0f * comp(q[M], i) + comp(uo, i);
-                    set_comp(g2, i, comp(gr, i) - comp(uf, i) * lapt * p.idt2);
+                for (int k = 0; k < (2 * P + 4) / 4; ++k) {
+                    const float4 v = ld4(lrow + 4 * lz + 4 * k);
+                    w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
                 }
-                st4(p.grad + base + col, g2);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 1; j <= M; ++j)
+                        lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+            }
+
+            float4 o;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], p.inv2dt);
+                if (z + i >= p.nz) v = 0.0f;
+                set_comp(o, i, v);
+            }
+            if (own) {
+                const int64_t base = (int64_t)x * sx;
+                st4s(p.out + base + col, o);
+                if (IMG) {
+                    float4 g2;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float lapt = comp(o, i) - 2.0f * comp(c, i) + comp(uo, i);
+                        set_comp(g2, i, comp(gr, i) - comp(uf, i) * lapt * p.idt2);
+                    }
+                    st4s(p.grad + base + col, g2);
+                }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 2 * M; ++j) q[j] = q[j + 1];
     }
 }
 
@@ -420,43 +400,117 @@ int grid_1d(int64_t n, int block) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
 }
 
+#ifndef WF_PF_LO
+#define WF_PF_LO 1
+#endif
+#ifndef WF_PF_HI
+#define WF_PF_HI 1
+#endif
+
+// Compiled 3D tile shapes (z threads x y threads): 128 x 8 nodes, whose rows
+// are whole 128-byte lines on line-aligned rows, and 64 x 16 nodes for thin
+// grids (fewer than 96 nodes along z). Measured on the 336^3 order-8 step,
+// 128 x 8 moves ~12% less data than 64 x 16 and ~8% less than 112 x 8.
+constexpr TileShape kTiles3[2] = {{32, 8}, {16, 16}};
+constexpr TileShape kTile2 = {64, 1};
+
+template <int M, int T, bool IMG>
+const void* step3_fn() {
+    constexpr int PF = M <= 4 ? WF_PF_LO : WF_PF_HI;
+    return reinterpret_cast<const void*>(&k_step<true, M, kTiles3[T].bz, kTiles3[T].by, PF, IMG>);
+}
+template <int M, bool IMG>
+const void* step2_fn() {
+    constexpr int PF = M <= 4 ? WF_PF_LO : WF_PF_HI;
+    return reinterpret_cast<const void*>(&k_step<false, M, kTile2.bz, kTile2.by, PF, IMG>);
+}
+
 template <int M>
-hipError_t launch_step_m(const StepParams& p, int ndim, bool img, hipStream_t s) {
-    const TileShape ts = step_tile(ndim, M);
-    const int grid = ((p.nblocks + 7) / 8) * 8;
-    if (ndim == 3) {
-        if (ts.bz != 16 || ts.by != 16) return hipErrorInvalidValue;
-        if (img) hipLaunchKernelGGL((k_step3d<M, 16, 16, true>), dim3(grid), dim3(256), 0, s, p);
-        else hipLaunchKernelGGL((k_step3d<M, 16, 16, false>), dim3(grid), dim3(256), 0, s, p);
-    } else {
-        if (ts.bz != 64) return hipErrorInvalidValue;
-        if (img) hipLaunchKernelGGL((k_step2d<M, 64, true>), dim3(grid), dim3(64), 0, s, p);
-        else hipLaunchKernelGGL((k_step2d<M, 64, false>), dim3(grid), dim3(64), 0, s, p);
+const void* step_fn_m(int ndim, int tile, bool img) {
+    if (ndim == 2) return img ? step2_fn<M, true>() : step2_fn<M, false>();
+    if (tile == 0) return img ? step3_fn<M, 0, true>() : step3_fn<M, 0, false>();
+    return img ? step3_fn<M, 1, true>() : step3_fn<M, 1, false>();
+}
+
+const void* step_fn(int ndim, int half, int tile, bool img) {
+    switch (half) {
+        case 2: return step_fn_m<2>(ndim, tile, img);
+        case 3: return step_fn_m<3>(ndim, tile, img);
+        case 4: return step_fn_m<4>(ndim, tile, img);
+        case 5: return step_fn_m<5>(ndim, tile, img);
+        case 6: return step_fn_m<6>(ndim, tile, img);
+        case 7: return step_fn_m<7>(ndim, tile, img);
+        case 8: return step_fn_m<8>(ndim, tile, img);
+        default: return nullptr;
     }
-    return hipGetLastError();
+}
+
+// Resident blocks of a step kernel on the whole device (cached).
+int step_capacity(int ndim, int half, int tile, bool img) {
+    static int cache[2][kMaxHalf + 1][2][2] = {};
+    static int cus = 0;
+    int& c = cache[ndim - 2][half][tile][img ? 1 : 0];
+    if (c > 0) return c;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    const TileShape ts = step_tile(ndim, tile);
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_fn(ndim, half, tile, img),
+                                                     ts.bz * ts.by, 0) != hipSuccess ||
+        per < 1)
+        per = 1;
+    c = per * cus;
+    return c;
 }
 
 }  // namespace
 
-TileShape step_tile(int ndim, int /*half*/) {
-    if (ndim == 3) return TileShape{16, 16};
-    return TileShape{64, 1};
+TileShape step_tile(int ndim, int tile) {
+    if (ndim == 3) return kTiles3[tile == 1 ? 1 : 0];
+    return kTile2;
 }
 
-void step_plan(StepParams& p, int ndim, int half, int cx_request) {
-    const TileShape ts = step_tile(ndim, half);
+void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request) {
+    int tile = 0;
+    if (ndim == 3) {
+        if (tile_request == 0 || tile_request == 1) {
+            tile = tile_request;
+        } else {
+            tile = p.nz < 96 ? 1 : 0;
+        }
+    }
+    p.tile = tile;
+    const TileShape ts = step_tile(ndim, tile);
     const int tz = 4 * ts.bz;
     p.ntz = (p.nz + tz - 1) / tz;
     p.nty = ndim == 3 ? (p.ny + ts.by - 1) / ts.by : 1;
     const int64_t tiles = (int64_t)p.ntz * p.nty;
     int cx = cx_request;
     if (cx <= 0) {
-        // enough blocks to fill 256 CUs several times over, but chunks long
-        // enough that the 2M-plane register warm-up stays a small overhead
-        const int64_t want = 2048;
-        int64_t nch = (want + tiles - 1) / tiles;
-        cx = (int)std::max<int64_t>(1, (p.nx + nch - 1) / nch);
-        cx = std::max(cx, std::min(p.nx, 6 * half));
+        // Chunks along x trade parallelism against the 2M + PF planes every
+        // chunk re-reads to fill its register ring. Cost model per resident
+        // round of blocks: (planes + warm-up) / occupancy, times the rounds.
+        const int cap = step_capacity(ndim, half, tile, imaging);
+        const int warm = 2 * half + 1;
+        double best = 1e300;
+        int best_n = 1;
+        for (int n = 1; n <= p.nx; ++n) {
+            const int c = (p.nx + n - 1) / n;
+            if (n > 1 && (p.nx + c - 1) / c != n) continue;   // same chunking as a smaller n
+            const double blocks = (double)tiles * n;
+            const double rounds = std::ceil(blocks / cap);
+            const double fill = std::min(1.0, blocks / cap);
+            const double cost = rounds * (c + warm) / fill;
+            if (cost < best * 0.999) {
+                best = cost;
+                best_n = n;
+            }
+        }
+        cx = (p.nx + best_n - 1) / best_n;
     }
     p.cx = std::min(cx, p.nx);
     p.nchunks = (p.nx + p.cx - 1) / p.cx;
@@ -465,16 +519,12 @@ void step_plan(StepParams& p, int ndim, int half, int cx_request) {
 
 hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s) {
     if (p.nblocks <= 0) return hipSuccess;
-    switch (half) {
-        case 2: return launch_step_m<2>(p, ndim, imaging, s);
-        case 3: return launch_step_m<3>(p, ndim, imaging, s);
-        case 4: return launch_step_m<4>(p, ndim, imaging, s);
-        case 5: return launch_step_m<5>(p, ndim, imaging, s);
-        case 6: return launch_step_m<6>(p, ndim, imaging, s);
-        case 7: return launch_step_m<7>(p, ndim, imaging, s);
-        case 8: return launch_step_m<8>(p, ndim, imaging, s);
-        default: return hipErrorInvalidValue;
-    }
+    const void* fn = step_fn(ndim, half, p.tile, imaging);
+    if (!fn) return hipErrorInvalidValue;
+    const TileShape ts = step_tile(ndim, p.tile);
+    const int grid = ((p.nblocks + 7) / 8) * 8;
+    void* args[] = {const_cast<StepParams*>(&p)};
+    return hipLaunchKernel(fn, dim3(grid), dim3(ts.bz * ts.by), args, 0, s);
 }
 
 hipError_t launch_inject(const InjectParams& p, hipStream_t s) {

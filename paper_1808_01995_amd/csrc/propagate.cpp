@@ -46,7 +46,7 @@ wf_status inject(const Model& md, const PointSet& ps, const float* vals, float* 
     if (ps.nnodes == 0) return WF_OK;
     InjectParams ip;
     ip.field = field;
-    ip.kap = md.d_kap.f();
+    ip.kap = md.kap();
     ip.off = ps.d_noff.as<int64_t>();
     ip.eta = ps.d_neta.f();
     ip.seg = ps.d_seg.as<int>();
@@ -76,8 +76,8 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
                       hipStream_t s) {
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
-    float* A = md.d_u[0].f();   // u^n
-    float* B = md.d_u[1].f();   // u^{n-1}, overwritten by u^{n+1}
+    float* A = md.u(0);   // u^n
+    float* B = md.u(1);   // u^{n-1}, overwritten by u^{n+1}
     WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
     WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
     if (rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, s), "fill"));
@@ -100,8 +100,8 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
                       const PointSet& src, float* src_out, hipStream_t s) {
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
-    float* A = md.d_u[0].f();   // v^{n+1}
-    float* B = md.d_u[1].f();   // v^{n+2}, overwritten by v^n
+    float* A = md.u(0);   // v^{n+1}
+    float* B = md.u(1);   // v^{n+2}, overwritten by v^n
     WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
     WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
     if (src.npts > 0)
@@ -122,17 +122,22 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
 // ---------------------------------------------------------------------------
 namespace {
 
-// A pool of pitched field buffers carved from one allocation.
+// A pool of pitched field buffers (with zero ghost planes) carved from one
+// allocation, zeroed once.
 struct FieldPool {
     DevBuf mem;
     int64_t stride = 0;   // floats per buffer
+    int64_t off = 0;      // plane 0 within a buffer
     int count = 0;
-    wf_status alloc(const Layout& L, int n) {
-        stride = (L.elems + 63) / 64 * 64;
+    wf_status alloc(const Layout& L, int n, hipStream_t s) {
+        stride = (L.alloc_elems + 63) / 64 * 64;
+        off = L.ghost_off;
         count = n;
-        return mem.alloc((int64_t)n * stride * 4 + 256);
+        wf_status st = mem.alloc((int64_t)n * stride * 4 + 256);
+        if (st != WF_OK) return st;
+        return hip_check(launch_fill(mem.f(), mem.bytes / 4, 0.0f, s), "fill");
     }
-    float* at(int i) const { return mem.f() + (int64_t)i * stride; }
+    float* at(int i) const { return mem.f() + (int64_t)i * stride + off; }
 };
 
 }  // namespace
@@ -141,10 +146,11 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
                        const PointSet& rec, const float* residual, float* grad_out, int n_ck,
                        int64_t budget, hipStream_t s) {
     const Layout& L = md.L;
-    const int64_t fb = ((L.elems + 63) / 64 * 64) * 4;
+    const int64_t fb = ((L.alloc_elems + 63) / 64 * 64) * 4;
     WF_TRY(md.ensure_kap(dt, s));
-    StepParams p;
+    StepParams p, pi;
     md.fill_step(p, dt);
+    md.fill_step(pi, dt, true);
     const int64_t l = nt - 1;                     // adjoint steps n = 0..nt-2
     if (l <= 0) {
         return hip_check(launch_fill(grad_out, L.npoints, 0.0f, s), "fill");
@@ -177,16 +183,15 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
     if (need > cap) return fail(WF_E_BUDGET, "gradient needs %lld bytes, %lld available", (long long)need, (long long)cap);
 
     FieldPool adj;
-    WF_TRY(adj.alloc(L, 3));
+    WF_TRY(adj.alloc(L, 3, s));
     float* V1 = adj.at(0);   // v^{n+1}
     float* V2 = adj.at(1);   // v^{n+2}, overwritten by v^n
     float* G = adj.at(2);    // gradient accumulator (pitched)
-    WF_TRY(hip_check(launch_fill(adj.mem.f(), 3 * adj.stride, 0.0f, s), "fill"));
     FieldPool pool;
-    WF_TRY(pool.alloc(L, nbuf));
+    WF_TRY(pool.alloc(L, nbuf, s));
 
     auto reverse_step = [&](int64_t n, const float* u_np1) -> wf_status {
-        WF_TRY(step(p, md, V1, V2, V2, true, G, u_np1, s));
+        WF_TRY(step(pi, md, V1, V2, V2, true, G, u_np1, s));
         WF_TRY(inject(md, rec, residual + (n + 1) * rec.npts, V2, G, u_np1, p, s));
         std::swap(V1, V2);
         return WF_OK;
@@ -194,7 +199,6 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
 
     if (store_all) {
         // buffer 0 is zero and stands for both u^0 and u^{-1}; buffer j holds u^j
-        WF_TRY(hip_check(launch_fill(pool.at(0), pool.stride, 0.0f, s), "fill"));
         for (int64_t n = 0; n + 1 < nt; ++n) {
             const float* cur = pool.at((int)n);
             const float* old = pool.at((int)std::max<int64_t>(n - 1, 0));
@@ -216,9 +220,7 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
                 if (pin[b] == 0 && b != avoid1 && b != avoid2) return b;
             return -1;
         };
-        // x_0: u^0 = u^{-1} = 0, one forward step injecting q^0
-        WF_TRY(hip_check(launch_fill(pool.at(0), pool.stride, 0.0f, s), "fill"));
-        WF_TRY(hip_check(launch_fill(pool.at(1), pool.stride, 0.0f, s), "fill"));
+        // x_0: u^0 = u^{-1} = 0 (the pool starts zeroed), one forward step injecting q^0
         WF_TRY(step(p, md, pool.at(0), pool.at(1), pool.at(1), false, nullptr, nullptr, s));
         WF_TRY(inject(md, src, src_wav, pool.at(1), nullptr, nullptr, p, s));
         bn = 1;

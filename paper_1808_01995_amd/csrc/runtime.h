@@ -45,10 +45,14 @@ struct Layout {
     int ndim = 3;
     int nx = 0, ny = 1, nz = 0;
     int64_t sx = 0, sy = 0;
-    int64_t elems = 0;     // pitched size in floats
-    int64_t npoints = 0;   // nx*ny*nz
+    int64_t elems = 0;        // pitched size of planes 0..nx-1 in floats
+    int64_t npoints = 0;      // nx*ny*nz
+    int64_t ghost_off = 0;    // kGhostPlanes * sx: plane 0 within an allocation
+    int64_t alloc_elems = 0;  // (nx + 2 kGhostPlanes) * sx
     void init(const wf_geom* g);
-    int64_t field_bytes() const { return elems * 4 + 256; }
+    int64_t field_bytes() const { return alloc_elems * 4 + 256; }
+    // plane 0 of a field allocation
+    float* field(void* alloc) const { return static_cast<float*>(alloc) + ghost_off; }
 };
 
 // Sparse points of one acquisition: a gather table for sampling and a
@@ -91,7 +95,9 @@ struct Model : public wf_model {
     wf_status check_dt(double dt) const;
     double vmax() const;
     wf_status points(int npts, const double* xyz, const wf::PointSet** out);
-    void fill_step(wf::StepParams& p, double dt) const;
+    void fill_step(wf::StepParams& p, double dt, bool imaging = false) const;
+    float* u(int i) const { return L.field(d_u[i].ptr); }
+    float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
         return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_etax.bytes + d_etay.bytes +
                d_etaz.bytes + d_scratch.bytes;

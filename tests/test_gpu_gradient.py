@@ -77,7 +77,7 @@ def test_gradient_budget_rejection_and_auto():
     assert e.value.status == _abi.WF_E_BUDGET
     fb = prop.npoints * 4
     g_small = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=0,
-                            hbm_budget_bytes=int(14 * fb))
+                            hbm_budget_bytes=int(30 * fb))
     g_all = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
     assert torch.equal(g_small, g_all)
 
