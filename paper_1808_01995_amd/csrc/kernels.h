@@ -43,7 +43,26 @@ struct StepParams {
     float inv2dt;
     float idt2;
     int tile;            // host side: which compiled tile shape step_plan chose
+
+    // Fused sampling of `cur`: the first smp_blocks blocks of the launch
+    // write smp_out[i] = sum_k smp_w[i*K+k] cur[smp_off[i*K+k]].
+    const int64_t* smp_off;
+    const float* smp_w;
+    float* smp_out;      // NULL: no sampling
+    int smp_n, smp_K, smp_blocks;
+
+    // Fused injection into `out`: nodes grouped by block (inj_blk, nblocks+1
+    // offsets), inside a block by (thread, x); thread t of block b owns the
+    // node range inj_thr[b*NT + t]. inj_inc holds this step's increments.
+    const int* inj_blk;  // NULL: no injection
+    const int2* inj_thr;
+    const int* inj_x;
+    const int* inj_comp;
+    const float* inj_inc;
 };
+
+// Largest number of injection nodes a block can stage in LDS.
+constexpr int kInjCap = 1024;
 
 // Tile shapes (threads along z carry 4 points each).
 struct TileShape {
@@ -52,8 +71,12 @@ struct TileShape {
 
 TileShape step_tile(int ndim, int tile);
 // Choose the tile shape and the x-chunking (ntz/nty/nchunks/nblocks/cx); a
-// positive cx_request forces the chunk length, tile_request >= 0 the shape.
-void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request);
+// positive cx_request forces the chunk length, tile_request >= 0 the shape;
+// reserve_blocks resident slots are left to the sampling blocks.
+void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request,
+               int reserve_blocks = 0);
+// Threads per block of the step kernel for a dimension and tile shape.
+int step_threads(int ndim, int tile);
 hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s);
 
 // Sparse injection at unique nodes (deterministic, no atomics):
@@ -75,6 +98,23 @@ struct InjectParams {
     float inv2dt, idt2;
 };
 hipError_t launch_inject(const InjectParams& p, hipStream_t s);
+
+// Increments of the fused injection for every step:
+//   inc[n * nnodes + k] = (sum_{e in seg k} w[e] vals[n * npts + pt[e]]) * kap/(1 + eta kap/(2 dt))
+// at node k (pitched offset off[k], damping eta[k]), n = 0..nrows-1.
+struct IncParams {
+    float* inc;
+    const float* kap;
+    const int64_t* off;
+    const float* eta;
+    const int* seg;
+    const int* pt;
+    const float* w;
+    const float* vals;
+    int nnodes, npts, nrows;
+    float inv2dt;
+};
+hipError_t launch_increments(const IncParams& p, hipStream_t s);
 
 // out[i] = sum_k w[i*K + k] * field[off[i*K + k]]
 hipError_t launch_sample(const float* field, const int64_t* off, const float* w, int npts,

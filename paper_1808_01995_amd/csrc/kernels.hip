@@ -110,8 +110,23 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
     constexpr int JY = NHY > 0 ? (NHY + NT - 1) / NT : 1;
     constexpr int JZ = (NHZ + NT - 1) / NT;
     __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];
+    __shared__ int inj_xl[kInjCap];
+    __shared__ int inj_cl[kInjCap];
+    __shared__ float inj_vl[kInjCap];
 
-    const int r = xcd_remap(blockIdx.x, p.nblocks);
+    if ((int)blockIdx.x < p.smp_blocks) {
+        // sampling role (the first blocks dispatched, spread over every XCD):
+        // interpolate the current field at the receivers
+        const int i = (int)blockIdx.x * NT + (int)threadIdx.x;
+        if (i < p.smp_n) {
+            float acc = 0.0f;
+            for (int k = 0; k < p.smp_K; ++k)
+                acc = fmaf(p.smp_w[(int64_t)i * p.smp_K + k], p.cur[p.smp_off[(int64_t)i * p.smp_K + k]], acc);
+            p.smp_out[i] = acc;
+        }
+        return;
+    }
+    const int r = xcd_remap((int)blockIdx.x - p.smp_blocks, p.nblocks);
     if (r >= p.nblocks) return;
     int t = r;
     const int itz = t % p.ntz;
@@ -176,6 +191,22 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
     for (int i = 0; i < 4; ++i)
         eyz[i] = (own && z + i < p.nz) ? ((D3 ? p.etay[y] : 0.0f) + p.etaz[z + i]) : 0.0f;
 
+    // this block's injection nodes -> LDS (read only after the first barrier)
+    int inj_i = 0, inj_e = 0;
+    if (p.inj_blk) {
+        const int b0 = p.inj_blk[r], b1 = p.inj_blk[r + 1];
+        if (b1 > b0) {
+            for (int i = tid; i < b1 - b0; i += NT) {
+                inj_xl[i] = p.inj_x[b0 + i];
+                inj_cl[i] = p.inj_comp[b0 + i];
+                inj_vl[i] = p.inj_inc[b0 + i];
+            }
+            const int2 rg = p.inj_thr[(int64_t)r * NT + tid];
+            inj_i = rg.x - b0;
+            inj_e = rg.y - b0;
+        }
+    }
+
     float4 ring[NQ];
 #pragma unroll
     for (int s = 0; s < 2 * M + PF; ++s) ring[s] = ld4(p.cur + (int64_t)(xb - M + s) * sx + col);
@@ -204,83 +235,104 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
 #pragma unroll
         for (int ph = 0; ph < NQ; ++ph) {
             const int x = xg + ph;
-            if (x >= xe) break;
-            // this plane's operands, loaded one plane ago
-            const float4 uo = uo_n, kp = kp_n, uf = uf_n, gr = gr_n;
-            const float ex = ex_n;
-            float4 hy[JY], hz[JZ];
+            if (x < xe) {   // uniform; a guarded body keeps the loop fully unrollable
+                // this plane's operands, loaded one plane ago
+                const float4 uo = uo_n, kp = kp_n, uf = uf_n, gr = gr_n;
+                const float ex = ex_n;
+                float4 hy[JY], hz[JZ];
 #pragma unroll
-            for (int j = 0; j < JY; ++j) hy[j] = hy_n[j];
+                for (int j = 0; j < JY; ++j) hy[j] = hy_n[j];
 #pragma unroll
-            for (int j = 0; j < JZ; ++j) hz[j] = hz_n[j];
-            load_next(x + 1);   // plane nx at the end is a ghost plane
-            ring[(ph + 2 * M + PF) % NQ] = ld4(p.cur + (int64_t)(x + M + PF) * sx + col);
-            const float4 c = ring[(ph + M) % NQ];
-            float* L = lds + (x & 1) * LBUF;
-            float* lrow = L + (ly + MY) * LW;
-            st4(lrow + P + 4 * lz, own ? c : zero4());
+                for (int j = 0; j < JZ; ++j) hz[j] = hz_n[j];
+                load_next(x + 1);   // plane nx at the end is a ghost plane
+                ring[(ph + 2 * M + PF) % NQ] = ld4(p.cur + (int64_t)(x + M + PF) * sx + col);
+                const float4 c = ring[(ph + M) % NQ];
+                float* L = lds + (x & 1) * LBUF;
+                float* lrow = L + (ly + MY) * LW;
+                st4(lrow + P + 4 * lz, own ? c : zero4());
 #pragma unroll
-            for (int j = 0; j < JY; ++j)
-                if (hy_l[j] >= 0) st4(L + hy_l[j], hy_v[j] ? hy[j] : zero4());
+                for (int j = 0; j < JY; ++j)
+                    if (hy_l[j] >= 0) st4(L + hy_l[j], hy_v[j] ? hy[j] : zero4());
 #pragma unroll
-            for (int j = 0; j < JZ; ++j)
-                if (hz_l[j] >= 0) st4(L + hz_l[j], hz_v[j] ? hz[j] : zero4());
-            __syncthreads();
+                for (int j = 0; j < JZ; ++j)
+                    if (hz_l[j] >= 0) st4(L + hz_l[j], hz_v[j] ? hz[j] : zero4());
+                __syncthreads();
 
-            float lap[4];
+                float lap[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) lap[i] = p.c0 * comp(c, i);
+                for (int i = 0; i < 4; ++i) lap[i] = p.c0 * comp(c, i);
 #pragma unroll
-            for (int j = 1; j <= M; ++j) {
-                const float4 a = ring[(ph + M - j) % NQ], b = ring[(ph + M + j) % NQ];
-                lap[0] = fmaf(p.wx[j], a.x + b.x, lap[0]);
-                lap[1] = fmaf(p.wx[j], a.y + b.y, lap[1]);
-                lap[2] = fmaf(p.wx[j], a.z + b.z, lap[2]);
-                lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
-            }
-            if (D3) {
-#pragma unroll
-                for (int j = 1; j <= MY; ++j) {
-                    const float4 a = ld4(lrow - j * LW + P + 4 * lz);
-                    const float4 b = ld4(lrow + j * LW + P + 4 * lz);
-                    lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
-                    lap[1] = fmaf(p.wy[j], a.y + b.y, lap[1]);
-                    lap[2] = fmaf(p.wy[j], a.z + b.z, lap[2]);
-                    lap[3] = fmaf(p.wy[j], a.w + b.w, lap[3]);
+                for (int j = 1; j <= M; ++j) {
+                    const float4 a = ring[(ph + M - j) % NQ], b = ring[(ph + M + j) % NQ];
+                    lap[0] = fmaf(p.wx[j], a.x + b.x, lap[0]);
+                    lap[1] = fmaf(p.wx[j], a.y + b.y, lap[1]);
+                    lap[2] = fmaf(p.wx[j], a.z + b.z, lap[2]);
+                    lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
                 }
-            }
-            {
-                float w[2 * P + 4];
+                if (D3) {
 #pragma unroll
-                for (int k = 0; k < (2 * P + 4) / 4; ++k) {
-                    const float4 v = ld4(lrow + 4 * lz + 4 * k);
-                    w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                    for (int j = 1; j <= MY; ++j) {
+                        const float4 a = ld4(lrow - j * LW + P + 4 * lz);
+                        const float4 b = ld4(lrow + j * LW + P + 4 * lz);
+                        lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
+                        lap[1] = fmaf(p.wy[j], a.y + b.y, lap[1]);
+                        lap[2] = fmaf(p.wy[j], a.z + b.z, lap[2]);
+                        lap[3] = fmaf(p.wy[j], a.w + b.w, lap[3]);
+                    }
                 }
+                {
+                    float w[2 * P + 4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                    for (int k = 0; k < (2 * P + 4) / 4; ++k) {
+                        const float4 v = ld4(lrow + 4 * lz + 4 * k);
+                        w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                    }
 #pragma unroll
-                    for (int j = 1; j <= M; ++j)
-                        lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
-            }
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 1; j <= M; ++j)
+                            lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+                }
 
-            float4 o;
+                float4 o;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], p.inv2dt);
-                if (z + i >= p.nz) v = 0.0f;
-                set_comp(o, i, v);
-            }
-            if (own) {
-                const int64_t base = (int64_t)x * sx;
-                st4s(p.out + base + col, o);
+                for (int i = 0; i < 4; ++i) {
+                    float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], p.inv2dt);
+                    if (z + i >= p.nz) v = 0.0f;
+                    set_comp(o, i, v);
+                }
+                float4 g2 = zero4();
                 if (IMG) {
-                    float4 g2;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const float lapt = comp(o, i) - 2.0f * comp(c, i) + comp(uo, i);
                         set_comp(g2, i, comp(gr, i) - comp(uf, i) * lapt * p.idt2);
                     }
-                    st4s(p.grad + base + col, g2);
+                }
+                // sources owned by this thread at this plane (rare, divergent)
+                // (at most one node per component; components are selected
+                // arithmetically and the loop has a fixed trip count, so neither
+                // the plane loop's unrolling nor register allocation is disturbed)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (!(inj_i < inj_e && inj_xl[inj_i] == x)) break;
+                    const int ci = inj_cl[inj_i];
+                    const float inc = inj_vl[inj_i];
+                    const float i0 = ci == 0 ? inc : 0.0f, i1 = ci == 1 ? inc : 0.0f;
+                    const float i2 = ci == 2 ? inc : 0.0f, i3 = ci == 3 ? inc : 0.0f;
+                    o.x += i0; o.y += i1; o.z += i2; o.w += i3;
+                    if (IMG) {
+                        g2.x -= uf.x * i0 * p.idt2;
+                        g2.y -= uf.y * i1 * p.idt2;
+                        g2.z -= uf.z * i2 * p.idt2;
+                        g2.w -= uf.w * i3 * p.idt2;
+                    }
+                    ++inj_i;
+                }
+                if (own) {
+                    const int64_t base = (int64_t)x * sx;
+                    st4s(p.out + base + col, o);
+                    if (IMG) st4s(p.grad + base + col, g2);
                 }
             }
         }
@@ -301,6 +353,21 @@ __global__ void k_inject(const InjectParams p) {
     const float inc = acc * (k * __builtin_amdgcn_rcpf(1.0f + g));
     p.field[o] += inc;
     if (p.grad) p.grad[o] -= p.ufwd[o] * inc * p.idt2;
+}
+
+__global__ void k_increments(const IncParams p) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.y;
+    if (k >= p.nnodes) return;
+    const float kk = p.kap[p.off[k]];
+    const float g = p.eta[k] * kk * p.inv2dt;
+    const float scale = kk * __builtin_amdgcn_rcpf(1.0f + g);
+    for (int row = n; row < p.nrows; row += gridDim.y) {
+        const float* v = p.vals + (int64_t)row * p.npts;
+        float acc = 0.0f;
+        for (int e = p.seg[k]; e < p.seg[k + 1]; ++e) acc = fmaf(p.w[e], v[p.pt[e]], acc);
+        p.inc[(int64_t)row * p.nnodes + k] = acc * scale;
+    }
 }
 
 __global__ void k_sample(const float* __restrict__ field, const int64_t* __restrict__ off,
@@ -463,18 +530,29 @@ int step_capacity(int ndim, int half, int tile, bool img) {
                                                      ts.bz * ts.by, 0) != hipSuccess ||
         per < 1)
         per = 1;
+    // Beyond 12 resident waves per CU the extra streams only compete for L2
+    // (halo rows get evicted before the neighbouring tile reads them): on the
+    // 336^3 order-8 step, 4 blocks/CU ran 10% slower than 3.
+    const int waves = ts.bz * ts.by / 64;
+    per = std::min(per, std::max(1, 12 / std::max(1, waves)));
     c = per * cus;
     return c;
 }
 
 }  // namespace
 
+int step_threads(int ndim, int tile) {
+    const TileShape t = step_tile(ndim, tile);
+    return t.bz * t.by;
+}
+
 TileShape step_tile(int ndim, int tile) {
     if (ndim == 3) return kTiles3[tile == 1 ? 1 : 0];
     return kTile2;
 }
 
-void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request) {
+void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request,
+               int reserve_blocks) {
     int tile = 0;
     if (ndim == 3) {
         if (tile_request == 0 || tile_request == 1) {
@@ -494,7 +572,10 @@ void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, 
         // Chunks along x trade parallelism against the 2M + PF planes every
         // chunk re-reads to fill its register ring. Cost model per resident
         // round of blocks: (planes + warm-up) / occupancy, times the rounds.
-        const int cap = step_capacity(ndim, half, tile, imaging);
+        // the sampling blocks of the launch are dispatched first and finish
+        // within microseconds, so they only take slots when they are many
+        const int full = step_capacity(ndim, half, tile, imaging);
+        const int cap = reserve_blocks > full / 4 ? std::max(full - reserve_blocks, full / 2) : full;
         const int warm = 2 * half + 1;
         double best = 1e300;
         int best_n = 1;
@@ -522,7 +603,7 @@ hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hi
     const void* fn = step_fn(ndim, half, p.tile, imaging);
     if (!fn) return hipErrorInvalidValue;
     const TileShape ts = step_tile(ndim, p.tile);
-    const int grid = ((p.nblocks + 7) / 8) * 8;
+    const int grid = p.smp_blocks + ((p.nblocks + 7) / 8) * 8;
     void* args[] = {const_cast<StepParams*>(&p)};
     return hipLaunchKernel(fn, dim3(grid), dim3(ts.bz * ts.by), args, 0, s);
 }
@@ -530,6 +611,13 @@ hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hi
 hipError_t launch_inject(const InjectParams& p, hipStream_t s) {
     if (p.nnodes <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_inject, dim3((p.nnodes + 255) / 256), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_increments(const IncParams& p, hipStream_t s) {
+    if (p.nnodes <= 0 || p.nrows <= 0) return hipSuccess;
+    dim3 g((p.nnodes + 255) / 256, (unsigned)std::min(p.nrows, 4096));
+    hipLaunchKernelGGL(k_increments, g, dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -69,6 +69,87 @@ wf_status sample(const PointSet& ps, const float* field, float* out, hipStream_t
                      "sample launch");
 }
 
+// Sources (or receivers in the adjoint) injected by the step kernel itself:
+// the per-step increments of every node are computed once per call, and the
+// owning thread adds its node's increment before storing the plane. Falls
+// back to the separate injection kernel when a block owns more nodes than it
+// can stage.
+struct Injector {
+    const PointSet* ps = nullptr;
+    const FusedInj* fz = nullptr;
+    const float* vals = nullptr;
+    const float* inc = nullptr;
+
+    wf_status prepare(Model& md, const PointSet& set, const StepParams& p, const float* series,
+                      int nrows, DevBuf& buf, hipStream_t s) {
+        ps = &set;
+        vals = series;
+        fz = nullptr;
+        if (set.nnodes == 0) return WF_OK;
+        if (std::getenv("WAVEFD_NO_FUSED_INJECT") == nullptr) {
+            WF_TRY(set.fused(md.L, p, &fz));
+            if (!fz->ok) fz = nullptr;
+        }
+        if (!fz) return WF_OK;
+        const int64_t need = (int64_t)nrows * fz->nnodes * 4;
+        if (buf.bytes < need) {
+            WF_TRY(hip_check(hipStreamSynchronize(s), "sync"));   // buffer may be in use
+            WF_TRY(buf.alloc(need));
+        }
+        IncParams ip;
+        ip.inc = buf.f();
+        ip.kap = md.kap();
+        ip.off = fz->off.as<int64_t>();
+        ip.eta = fz->eta.f();
+        ip.seg = fz->seg.as<int>();
+        ip.pt = fz->pt.as<int>();
+        ip.w = fz->w.f();
+        ip.vals = series;
+        ip.nnodes = fz->nnodes;
+        ip.npts = set.npts;
+        ip.nrows = nrows;
+        ip.inv2dt = p.inv2dt;
+        inc = buf.f();
+        return hip_check(launch_increments(ip, s), "increments");
+    }
+    // configure the step that injects row `row`
+    void configure(StepParams& p, int64_t row) const {
+        p.inj_blk = nullptr;
+        if (!fz) return;
+        p.inj_blk = fz->blk.as<int>();
+        p.inj_thr = fz->thr.as<int2>();
+        p.inj_x = fz->x.as<int>();
+        p.inj_comp = fz->comp.as<int>();
+        p.inj_inc = inc + row * fz->nnodes;
+    }
+    // after the step: the separate kernel when not fused
+    wf_status after(const Model& md, int64_t row, float* field, float* grad, const float* ufwd,
+                    const StepParams& p, hipStream_t s) const {
+        if (fz || !ps || ps->nnodes == 0) return WF_OK;
+        return inject(md, *ps, vals + row * ps->npts, field, grad, ufwd, p, s);
+    }
+};
+
+void set_sampling(StepParams& p, const PointSet* ps, float* out, int NT) {
+    if (!ps || ps->npts == 0 || !out) {
+        p.smp_out = nullptr;
+        p.smp_blocks = 0;
+        p.smp_n = 0;
+        return;
+    }
+    p.smp_off = ps->d_off.as<int64_t>();
+    p.smp_w = ps->d_w.f();
+    p.smp_out = out;
+    p.smp_n = ps->npts;
+    p.smp_K = ps->K;
+    p.smp_blocks = (ps->npts + NT - 1) / NT;
+}
+
+int block_threads(const Model& md, const StepParams& p) {
+    const TileShape ts = step_tile(md.geom.ndim, p.tile);
+    return ts.bz * ts.by;
+}
+
 }  // namespace
 
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
@@ -80,19 +161,25 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
     float* B = md.u(1);   // u^{n-1}, overwritten by u^{n+1}
     WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
     WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
-    if (rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, s), "fill"));
     if (u_save) WF_TRY(hip_check(launch_fill(u_save, L.npoints, 0.0f, s), "fill"));
     StepParams p;
-    md.fill_step(p, dt);
+    md.fill_step(p, dt, false, rec.npts);
+    const int NT = block_threads(md, p);
+    Injector inj;
+    WF_TRY(inj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
+    if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, s), "fill"));
     for (int n = 0; n + 1 < nt; ++n) {
+        // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
+        inj.configure(p, n);
+        set_sampling(p, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr, NT);
         WF_TRY(step(p, md, A, B, B, false, nullptr, nullptr, s));
-        WF_TRY(inject(md, src, src_wav + (int64_t)n * src.npts, B, nullptr, nullptr, p, s));
-        WF_TRY(sample(rec, B, rec_out + (int64_t)(n + 1) * rec.npts, s));
+        WF_TRY(inj.after(md, n, B, nullptr, nullptr, p, s));
         if (u_save && (n + 1) % save_every == 0)
             WF_TRY(hip_check(launch_unpitch(B, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
                                             L.nx, L.ny, L.nz, L.sx, L.sy, s), "save"));
         std::swap(A, B);
     }
+    if (nt > 1) WF_TRY(sample(rec, A, rec_out + (int64_t)(nt - 1) * rec.npts, s));
     return WF_OK;
 }
 
@@ -104,16 +191,21 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
     float* B = md.u(1);   // v^{n+2}, overwritten by v^n
     WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
     WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
-    if (src.npts > 0)
-        WF_TRY(hip_check(launch_fill(src_out + (int64_t)(nt - 1) * src.npts, src.npts, 0.0f, s), "fill"));
     StepParams p;
-    md.fill_step(p, dt);
+    md.fill_step(p, dt, false, src.npts);
+    const int NT = block_threads(md, p);
+    Injector inj;
+    WF_TRY(inj.prepare(md, rec, p, rec_in, nt, md.d_inc[0], s));
+    if (nt == 1 && src.npts > 0) WF_TRY(hip_check(launch_fill(src_out, src.npts, 0.0f, s), "fill"));
     for (int n = nt - 2; n >= 0; --n) {
+        // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
+        inj.configure(p, n + 1);
+        set_sampling(p, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr, NT);
         WF_TRY(step(p, md, A, B, B, false, nullptr, nullptr, s));
-        WF_TRY(inject(md, rec, rec_in + (int64_t)(n + 1) * rec.npts, B, nullptr, nullptr, p, s));
-        WF_TRY(sample(src, B, src_out + (int64_t)n * src.npts, s));
+        WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, p, s));
         std::swap(A, B);
     }
+    if (nt > 1) WF_TRY(sample(src, A, src_out, s));
     return WF_OK;
 }
 
@@ -189,10 +281,21 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
     float* G = adj.at(2);    // gradient accumulator (pitched)
     FieldPool pool;
     WF_TRY(pool.alloc(L, nbuf, s));
+    Injector qinj, rinj;   // sources in forward steps, residual in adjoint steps
+    WF_TRY(qinj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
+    WF_TRY(rinj.prepare(md, rec, pi, residual, nt, md.d_inc[1], s));
 
+    // forward step n: u^{n+1} into `out` from u^n, u^{n-1}, injecting q^n
+    auto forward_step = [&](int64_t n, const float* cur, const float* old, float* out) -> wf_status {
+        qinj.configure(p, n);
+        WF_TRY(step(p, md, cur, old, out, false, nullptr, nullptr, s));
+        return qinj.after(md, n, out, nullptr, nullptr, p, s);
+    };
+    // adjoint step n with imaging of term j = n+1 (u^{n+1} given)
     auto reverse_step = [&](int64_t n, const float* u_np1) -> wf_status {
+        rinj.configure(pi, n + 1);
         WF_TRY(step(pi, md, V1, V2, V2, true, G, u_np1, s));
-        WF_TRY(inject(md, rec, residual + (n + 1) * rec.npts, V2, G, u_np1, p, s));
+        WF_TRY(rinj.after(md, n + 1, V2, G, u_np1, pi, s));
         std::swap(V1, V2);
         return WF_OK;
     };
@@ -202,9 +305,7 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
         for (int64_t n = 0; n + 1 < nt; ++n) {
             const float* cur = pool.at((int)n);
             const float* old = pool.at((int)std::max<int64_t>(n - 1, 0));
-            float* out = pool.at((int)(n + 1));
-            WF_TRY(step(p, md, cur, old, out, false, nullptr, nullptr, s));
-            WF_TRY(inject(md, src, src_wav + n * src.npts, out, nullptr, nullptr, p, s));
+            WF_TRY(forward_step(n, cur, old, pool.at((int)(n + 1))));
         }
         for (int64_t n = nt - 2; n >= 0; --n) WF_TRY(reverse_step(n, pool.at((int)(n + 1))));
     } else {
@@ -221,8 +322,7 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
             return -1;
         };
         // x_0: u^0 = u^{-1} = 0 (the pool starts zeroed), one forward step injecting q^0
-        WF_TRY(step(p, md, pool.at(0), pool.at(1), pool.at(1), false, nullptr, nullptr, s));
-        WF_TRY(inject(md, src, src_wav, pool.at(1), nullptr, nullptr, p, s));
+        WF_TRY(forward_step(0, pool.at(0), pool.at(1), pool.at(1)));
         bn = 1;
         bo = 0;
         int64_t pos = 0;
@@ -234,8 +334,7 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
                         // forward step F_{i+1}: u^{i+2} from u^{i+1} (bn), u^i (bo), q^{i+1}
                         int out = pin[bo] == 0 ? bo : take_free(bn, bo);
                         if (out < 0) return fail(WF_E_STATE, "revolve: buffer pool exhausted");
-                        WF_TRY(step(p, md, pool.at(bn), pool.at(bo), pool.at(out), false, nullptr, nullptr, s));
-                        WF_TRY(inject(md, src, src_wav + (i + 1) * src.npts, pool.at(out), nullptr, nullptr, p, s));
+                        WF_TRY(forward_step(i + 1, pool.at(bn), pool.at(bo), pool.at(out)));
                         bo = bn;
                         bn = out;
                     }

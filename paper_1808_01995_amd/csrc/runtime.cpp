@@ -272,6 +272,98 @@ wf_status PointSet::build(const wf_geom* g, const Layout& L, int npts_, const do
     if ((st = d_seg.upload(seg.data(), (int64_t)seg.size() * 4)) != WF_OK) return st;
     if ((st = d_ept.upload(ept.data(), (int64_t)ept.size() * 4)) != WF_OK) return st;
     if ((st = d_ew.upload(ew.data(), (int64_t)ew.size() * 4)) != WF_OK) return st;
+    h_noff = std::move(noff);
+    h_neta = std::move(neta);
+    h_seg = std::move(seg);
+    h_ept = std::move(ept);
+    h_ew = std::move(ew);
+    return WF_OK;
+}
+
+PointSet::~PointSet() {
+    for (FusedInj* f : fused_cache) delete f;
+}
+
+wf_status PointSet::fused(const Layout& L, const StepParams& p, const FusedInj** out) const {
+    *out = nullptr;
+    const TileShape ts = step_tile(L.ndim, p.tile);
+    const int NT = ts.bz * ts.by, TZ = 4 * ts.bz, TY = ts.by;
+    const int64_t key[6] = {p.tile, p.ntz, p.nty, p.cx, p.nchunks, NT};
+    for (FusedInj* f : fused_cache)
+        if (std::equal(key, key + 6, f->key)) {
+            *out = f;
+            return WF_OK;
+        }
+    FusedInj* f = new (std::nothrow) FusedInj();
+    if (!f) return fail(WF_E_NOMEM, "host allocation");
+    std::copy(key, key + 6, f->key);
+    // owner of every unique node: block, thread, plane, component
+    struct Own { int64_t blk; int tid; int x; int comp; int node; };
+    std::vector<Own> own((size_t)nnodes);
+    for (int k = 0; k < nnodes; ++k) {
+        const int64_t o = h_noff[(size_t)k];
+        const int x = (int)(o / L.sx);
+        const int64_t rem = o % L.sx;
+        const int y = (int)(rem / L.sy), z = (int)(rem % L.sy);
+        const int itz = z / TZ, ity = y / TY, ich = x / p.cx;
+        const int64_t b = ((int64_t)ich * p.nty + ity) * p.ntz + itz;
+        const int zz = z - itz * TZ;
+        own[(size_t)k] = {b, (y - ity * TY) * ts.bz + zz / 4, x, zz % 4, k};
+    }
+    std::sort(own.begin(), own.end(), [](const Own& a, const Own& b) {
+        if (a.blk != b.blk) return a.blk < b.blk;
+        if (a.tid != b.tid) return a.tid < b.tid;
+        if (a.x != b.x) return a.x < b.x;
+        return a.comp < b.comp;
+    });
+    std::vector<int> blk((size_t)p.nblocks + 1, 0), xs, comps, segs(1, 0), pts;
+    std::vector<int2> thr((size_t)p.nblocks * NT, make_int2(0, 0));
+    std::vector<int64_t> offs;
+    std::vector<float> etas, ws;
+    f->ok = true;
+    size_t i = 0;
+    for (int64_t b = 0; b < p.nblocks; ++b) {
+        blk[(size_t)b] = (int)i;
+        const size_t b0 = i;
+        while (i < own.size() && own[i].blk == b) {
+            const size_t t0 = i;
+            const int tid = own[i].tid;
+            while (i < own.size() && own[i].blk == b && own[i].tid == tid) {
+                const Own& w = own[i];
+                xs.push_back(w.x);
+                comps.push_back(w.comp);
+                offs.push_back(h_noff[(size_t)w.node]);
+                etas.push_back(h_neta[(size_t)w.node]);
+                for (int e = h_seg[(size_t)w.node]; e < h_seg[(size_t)w.node + 1]; ++e) {
+                    pts.push_back(h_ept[(size_t)e]);
+                    ws.push_back(h_ew[(size_t)e]);
+                }
+                segs.push_back((int)pts.size());
+                ++i;
+            }
+            thr[(size_t)(b * NT + tid)] = make_int2((int)t0, (int)i);
+        }
+        if (i - b0 > (size_t)kInjCap) f->ok = false;
+    }
+    blk[(size_t)p.nblocks] = (int)i;
+    f->nnodes = (int)i;
+    wf_status st;
+    if (f->ok) {
+        if ((st = f->blk.upload(blk.data(), (int64_t)blk.size() * 4)) != WF_OK ||
+            (st = f->thr.upload(thr.data(), (int64_t)thr.size() * 8)) != WF_OK ||
+            (st = f->x.upload(xs.data(), (int64_t)xs.size() * 4)) != WF_OK ||
+            (st = f->comp.upload(comps.data(), (int64_t)comps.size() * 4)) != WF_OK ||
+            (st = f->off.upload(offs.data(), (int64_t)offs.size() * 8)) != WF_OK ||
+            (st = f->eta.upload(etas.data(), (int64_t)etas.size() * 4)) != WF_OK ||
+            (st = f->seg.upload(segs.data(), (int64_t)segs.size() * 4)) != WF_OK ||
+            (st = f->pt.upload(pts.data(), (int64_t)pts.size() * 4)) != WF_OK ||
+            (st = f->w.upload(ws.data(), (int64_t)ws.size() * 4)) != WF_OK) {
+            delete f;
+            return st;
+        }
+    }
+    fused_cache.push_back(f);
+    *out = f;
     return WF_OK;
 }
 
@@ -406,7 +498,7 @@ Model::~Model() {
     for (auto& c : pcache) delete c.ps;
 }
 
-void Model::fill_step(StepParams& p, double dt, bool imaging) const {
+void Model::fill_step(StepParams& p, double dt, bool imaging, int sample_points) const {
     std::memset(&p, 0, sizeof p);
     p.kap = kap();
     p.etax = d_etax.f();
@@ -433,5 +525,12 @@ void Model::fill_step(StepParams& p, double dt, bool imaging) const {
     int cx = 0, tile = -1;
     if (const char* s = std::getenv("WAVEFD_CX")) cx = std::atoi(s);
     if (const char* s = std::getenv("WAVEFD_TILE")) tile = std::atoi(s);
-    step_plan(p, geom.ndim, half, imaging, cx, tile);
+    // the sampling blocks of the same launch reserve resident slots
+    int reserve = 0;
+    if (sample_points > 0) {
+        const int tz = tile >= 0 ? tile : (geom.ndim == 3 && L.nz < 96 ? 1 : 0);
+        const int nt = step_threads(geom.ndim, tz);
+        reserve = (sample_points + nt - 1) / nt;
+    }
+    step_plan(p, geom.ndim, half, imaging, cx, tile, reserve);
 }

@@ -55,13 +55,34 @@ struct Layout {
     float* field(void* alloc) const { return static_cast<float*>(alloc) + ghost_off; }
 };
 
+// Injection nodes of a point set arranged for the fused step kernel of one
+// launch plan: nodes grouped by block, by owning thread and by x inside a
+// block, plus everything the increment kernel needs in that order.
+struct FusedInj {
+    int64_t key[6] = {0, 0, 0, 0, 0, 0};   // plan: tile, ntz, nty, cx, nchunks, NT
+    bool ok = false;                       // false: a block exceeds the LDS cap
+    int nnodes = 0;
+    DevBuf blk, thr, x, comp;              // block offsets, per-thread ranges, plane, component
+    DevBuf off, eta, seg, pt, w;           // increment inputs in the same order
+};
+
 // Sparse points of one acquisition: a gather table for sampling and a
 // node-grouped table for deterministic injection.
 struct PointSet {
     int npts = 0, K = 0, nnodes = 0;
     DevBuf d_off, d_w;                          // [npts*K]
     DevBuf d_noff, d_neta, d_seg, d_ept, d_ew;  // injection by node
+    std::vector<int64_t> h_noff;                // host copies of the node tables
+    std::vector<float> h_neta, h_ew;
+    std::vector<int> h_seg, h_ept;
+    mutable std::vector<FusedInj*> fused_cache;
     wf_status build(const wf_geom* g, const Layout& L, int npts, const double* xyz);
+    // tables for the fused injection of launch plan p (nullptr on failure)
+    wf_status fused(const Layout& L, const StepParams& p, const FusedInj** out) const;
+    PointSet() = default;
+    PointSet(const PointSet&) = delete;
+    PointSet& operator=(const PointSet&) = delete;
+    ~PointSet();
 };
 
 }  // namespace wf
@@ -83,6 +104,7 @@ struct Model : public wf_model {
     wf::Layout L;
     double alpha[wf::kMaxHalf + 1]{};
     wf::DevBuf d_m, d_kap, d_u[2], d_etax, d_etay, d_etaz, d_scratch;
+    wf::DevBuf d_inc[2];   // precomputed injection increments (grow-only, stream-ordered reuse)
     float m_min = 0.f, m_max = 0.f;
     double kap_dt = -1.0;
     std::vector<PCache> pcache;
@@ -95,12 +117,13 @@ struct Model : public wf_model {
     wf_status check_dt(double dt) const;
     double vmax() const;
     wf_status points(int npts, const double* xyz, const wf::PointSet** out);
-    void fill_step(wf::StepParams& p, double dt, bool imaging = false) const;
+    // plan a step launch; sample_points > 0 leaves room for that many fused samples
+    void fill_step(wf::StepParams& p, double dt, bool imaging = false, int sample_points = 0) const;
     float* u(int i) const { return L.field(d_u[i].ptr); }
     float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
         return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_etax.bytes + d_etay.bytes +
-               d_etaz.bytes + d_scratch.bytes;
+               d_etaz.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes;
     }
 };
 
