@@ -1,25 +1,512 @@
-// Serving engine entry points (continuous batching). Implemented in a later
-// revision; every call reports WF_E_STATE until then.
+// Serving engine: continuous batching of forward and gradient requests on one
+// GPU under an HBM budget.
+//
+// * The budget is one device allocation made at creation, sub-allocated on the
+//   host (no hipMalloc/hipFree while serving, so no device-wide syncs).
+// * submit() queues a request; admission is FIFO by footprint against the
+//   budget and the slot limit, re-run whenever a request completes.
+// * Small forward shots (<= kSmallPoints computational nodes) are batched: a
+//   batcher thread advances every active small grid together, kBatchSteps
+//   time steps per iteration, one k_step_batch launch per step per (dimension,
+//   order, tile) group; requests join and leave between iterations, so
+//   arrivals are admitted while others are on the GPU and their steps share
+//   launches. The arithmetic of every grid is independent of the batch.
+// * Other requests (large grids, gradients) run on worker threads, each with
+//   its own non-blocking stream, concurrently with the batch.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <new>
+#include <thread>
+#include <vector>
+
 #include "runtime.h"
+
+namespace wf {
+
+// ---------------------------------------------------------------------------
+// arena
+// ---------------------------------------------------------------------------
+struct Arena {
+    char* base = nullptr;
+    int64_t size = 0;
+    int64_t used = 0;
+    std::mutex mu;
+    std::map<int64_t, int64_t> free_;   // offset -> size
+    std::map<int64_t, int64_t> live;    // offset -> size
+};
+
+Arena* arena_create(int64_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(WF_E_NOMEM, "cannot allocate a %lld-byte device arena", (long long)bytes);
+        return nullptr;
+    }
+    Arena* a = new (std::nothrow) Arena();
+    if (!a) {
+        hipFree(p);
+        fail(WF_E_NOMEM, "host allocation");
+        return nullptr;
+    }
+    a->base = static_cast<char*>(p);
+    a->size = bytes;
+    a->free_[0] = bytes;
+    return a;
+}
+
+void arena_destroy(Arena* a) {
+    if (!a) return;
+    hipFree(a->base);
+    delete a;
+}
+
+void* arena_alloc(Arena* a, int64_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    std::lock_guard<std::mutex> lk(a->mu);
+    for (auto it = a->free_.begin(); it != a->free_.end(); ++it) {
+        if (it->second >= bytes) {
+            const int64_t off = it->first, sz = it->second;
+            a->free_.erase(it);
+            if (sz > bytes) a->free_[off + bytes] = sz - bytes;
+            a->live[off] = bytes;
+            a->used += bytes;
+            return a->base + off;
+        }
+    }
+    return nullptr;
+}
+
+void arena_free(Arena* a, void* p) {
+    std::lock_guard<std::mutex> lk(a->mu);
+    const int64_t off = static_cast<char*>(p) - a->base;
+    auto it = a->live.find(off);
+    if (it == a->live.end()) return;
+    int64_t start = off, sz = it->second;
+    a->used -= sz;
+    a->live.erase(it);
+    auto nx = a->free_.lower_bound(start);
+    if (nx != a->free_.end() && nx->first == start + sz) {
+        sz += nx->second;
+        nx = a->free_.erase(nx);
+    }
+    if (nx != a->free_.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == start) {
+            start = pv->first;
+            sz += pv->second;
+            a->free_.erase(pv);
+        }
+    }
+    a->free_[start] = sz;
+}
+
+int64_t arena_used(const Arena* a) { return a ? a->used : 0; }
+
+int64_t arena_largest_free(Arena* a) {
+    std::lock_guard<std::mutex> lk(a->mu);
+    int64_t m = 0;
+    for (auto& kv : a->free_) m = std::max(m, kv.second);
+    return m;
+}
+
+}  // namespace wf
 
 using namespace wf;
 
+namespace {
+
+constexpr int64_t kSmallPoints = (int64_t)1 << 24;   // batched if the grid has at most this many nodes
+constexpr int kBatchSteps = 32;                        // steps per batch iteration
+constexpr int kWorkers = 2;                            // threads for large requests and gradients
+
+struct EJob {
+    uint64_t ticket = 0;
+    wf_request rq{};
+    std::vector<double> src, rec;
+    bool small = false;
+    int64_t foot = 0;       // bytes reserved at admission
+    int64_t grad_cap = 0;   // bytes the gradient's checkpoints may use
+    wf_status st = WF_OK;
+    Model* md = nullptr;
+    BatchFwd bf;
+    const PointSet* ps_src = nullptr;
+    const PointSet* ps_rec = nullptr;
+};
+
+int64_t field_bytes_of(const wf_geom* g) {
+    Layout L;
+    L.init(g);
+    return L.field_bytes();
+}
+
+}  // namespace
+
+struct wf_engine {
+    Arena* arena = nullptr;
+    int64_t budget = 0;
+    int max_slots = 1;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work;
+    std::condition_variable cv_done;
+    std::deque<EJob*> pending;
+    std::deque<EJob*> small_ready;
+    std::deque<EJob*> large_ready;
+    std::deque<std::pair<uint64_t, wf_status>> done;
+    int64_t reserved = 0;
+    int running = 0;
+    int64_t completed = 0;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::vector<std::thread> threads;
+
+    // FIFO admission (caller holds mu)
+    void admit() {
+        while (!pending.empty() && running < max_slots && reserved + pending.front()->foot <= budget) {
+            EJob* j = pending.front();
+            pending.pop_front();
+            reserved += j->foot;
+            ++running;
+            (j->small ? small_ready : large_ready).push_back(j);
+        }
+        cv_work.notify_all();
+    }
+
+    void complete(EJob* j) {
+        std::lock_guard<std::mutex> lk(mu);
+        reserved -= j->foot;
+        --running;
+        ++completed;
+        done.emplace_back(j->ticket, j->st);
+        delete j;
+        admit();
+        cv_done.notify_all();
+    }
+
+    void run_large(EJob* j, hipStream_t s);
+    void worker();
+    void batcher();
+};
+
+// footprint estimate of a request (bytes of the arena it may occupy)
+static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
+    Layout L;
+    L.init(&r->geom);
+    const int64_t fb = L.field_bytes();
+    const int64_t dense = L.npoints * 4;
+    const int K = 1 << r->geom.ndim;
+    const int64_t pts = (int64_t)(r->nsrc + r->nrec) * K;
+    const int64_t tables = pts * 64 + (int64_t)L.nx * 4 * 1024 + ((int64_t)16 << 20);
+    const int64_t inc_src = (int64_t)r->nt * r->nsrc * K * 4;
+    const int64_t inc_rec = (int64_t)r->nt * r->nrec * K * 4;
+    const int64_t model = dense + 3 * fb + ((int64_t)1 << 20);
+    if (r->kind == WF_REQ_FORWARD) {
+        j->foot = model + inc_src + tables;
+        j->small = L.npoints <= kSmallPoints;
+    } else {
+        // forward record + residual, both increment tables, adjoint pair and
+        // gradient, and a checkpoint pool of up to 2*32+3 fields (store-all if it fits)
+        const int64_t l = r->nt - 1;
+        const int64_t fixed = model + inc_src + inc_rec + (int64_t)r->nt * r->nrec * 4 + 3 * fb + tables;
+        int64_t pool = std::min<int64_t>(l + 1, 2 * 32 + 3) * fb;
+        if (fixed + pool > budget) pool = 5 * fb;   // one snapshot, the minimum
+        j->grad_cap = 3 * fb + pool + ((int64_t)1 << 20);
+        j->foot = fixed + pool;
+        j->small = false;
+    }
+    if (j->foot > budget)
+        return fail(WF_E_BUDGET, "request needs about %lld bytes, the engine budget is %lld",
+                    (long long)j->foot, (long long)budget);
+    return WF_OK;
+}
+
+void wf_engine::run_large(EJob* j, hipStream_t s) {
+    const wf_request& r = j->rq;
+    Model* md = new (std::nothrow) Model();
+    wf_status st = md ? md->init(&r.geom, r.m_dev, s) : fail(WF_E_NOMEM, "host allocation");
+    const PointSet *src = nullptr, *rec = nullptr;
+    if (st == WF_OK) st = md->check_dt(r.dt);
+    if (st == WF_OK) st = md->points(r.nsrc, j->src.data(), &src);
+    if (st == WF_OK) st = md->points(r.nrec, j->rec.data(), &rec);
+    if (st == WF_OK && r.kind == WF_REQ_FORWARD) {
+        st = run_forward(*md, r.dt, r.nt, *src, r.src_wav, *rec, r.rec_out, nullptr, 1, s);
+        if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+    } else if (st == WF_OK) {
+        const int64_t n = (int64_t)r.nt * r.nrec;
+        DevBuf res, part;
+        st = res.alloc(n * 4 + 256);
+        if (st == WF_OK) st = part.alloc((int64_t)residual_blocks(n) * 8 + 256);
+        if (st == WF_OK) st = run_forward(*md, r.dt, r.nt, *src, r.src_wav, *rec, res.f(), nullptr, 1, s);
+        if (st == WF_OK && r.rec_out)
+            st = hip_check(launch_copy(res.f(), r.rec_out, n, s), "copy record");
+        if (st == WF_OK && n > 0) {
+            std::vector<double> ph((size_t)residual_blocks(n));
+            st = hip_check(launch_residual(res.f(), r.d_obs, res.f(), n, part.as<double>(), s), "residual");
+            if (st == WF_OK)
+                st = hip_check(hipMemcpyAsync(ph.data(), part.ptr, ph.size() * 8, hipMemcpyDeviceToHost, s), "misfit");
+            if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+            double phi = 0.0;
+            for (double v : ph) phi += v;
+            if (st == WF_OK && r.misfit_out) *r.misfit_out = 0.5 * phi;
+        }
+        if (st == WF_OK)
+            st = run_gradient(*md, r.dt, r.nt, *src, r.src_wav, *rec, res.f(), r.grad_out, 0, j->grad_cap, s);
+        if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+    }
+    delete md;   // waits for the model's stream
+    j->st = st;
+}
+
+void wf_engine::worker() {
+    (void)hipSetDevice(device);
+    set_thread_arena(arena);
+    hipStream_t s = nullptr;
+    (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    for (;;) {
+        EJob* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !large_ready.empty(); });
+            if (large_ready.empty()) break;   // stop requested and nothing left
+            j = large_ready.front();
+            large_ready.pop_front();
+        }
+        run_large(j, s);
+        complete(j);
+    }
+    (void)hipStreamDestroy(s);
+    set_thread_arena(nullptr);
+}
+
+void wf_engine::batcher() {
+    (void)hipSetDevice(device);
+    set_thread_arena(arena);
+    hipStream_t s = nullptr;
+    (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    BatchJob* host_tab = nullptr;
+    int cap_tab = 0;
+    DevBuf dev_tab;
+    std::vector<EJob*> active;
+    for (;;) {
+        std::vector<EJob*> fresh;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (active.empty())
+                cv_work.wait(lk, [&] { return stop || !small_ready.empty(); });
+            while (!small_ready.empty()) {
+                fresh.push_back(small_ready.front());
+                small_ready.pop_front();
+            }
+            if (active.empty() && fresh.empty() && stop) break;
+        }
+        // set up newly admitted grids (their first step joins this iteration)
+        for (EJob* j : fresh) {
+            const wf_request& r = j->rq;
+            j->md = new (std::nothrow) Model();
+            wf_status st = j->md ? j->md->init(&r.geom, r.m_dev, s) : fail(WF_E_NOMEM, "host allocation");
+            if (st == WF_OK) st = j->md->check_dt(r.dt);
+            if (st == WF_OK) st = j->md->points(r.nsrc, j->src.data(), &j->ps_src);
+            if (st == WF_OK) st = j->md->points(r.nrec, j->rec.data(), &j->ps_rec);
+            if (st == WF_OK)
+                st = batch_forward_begin(*j->md, r.dt, r.nt, *j->ps_src, r.src_wav, *j->ps_rec, r.rec_out, s, j->bf);
+            if (st == WF_E_STATE) {
+                // not batchable (too many sources in one block): run it alone
+                st = run_forward(*j->md, r.dt, r.nt, *j->ps_src, r.src_wav, *j->ps_rec, r.rec_out, nullptr, 1, s);
+                if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+                j->bf.n = r.nt - 1;
+                j->bf.nt = r.nt;
+                j->bf.rec = nullptr;
+            }
+            j->st = st;
+            active.push_back(j);
+        }
+        // one iteration: kBatchSteps steps of every active grid
+        std::map<std::tuple<int, int, int>, std::vector<EJob*>> groups;
+        for (EJob* j : active)
+            if (j->st == WF_OK && j->bf.n < j->bf.nt - 1)
+                groups[std::make_tuple(j->md->geom.ndim, j->md->half, j->bf.p.tile)].push_back(j);
+        int ntab = 0;
+        for (auto& g : groups) ntab += (int)g.second.size();
+        wf_status st = WF_OK;
+        if (ntab > 0) {
+            if (ntab > cap_tab) {
+                if (host_tab) (void)hipHostFree(host_tab);
+                cap_tab = std::max(ntab, 2 * cap_tab);
+                if (hipHostMalloc(reinterpret_cast<void**>(&host_tab), sizeof(BatchJob) * cap_tab) != hipSuccess) {
+                    host_tab = nullptr;
+                    cap_tab = 0;
+                    st = fail(WF_E_NOMEM, "pinned host table");
+                }
+                if (st == WF_OK) st = dev_tab.alloc((int64_t)sizeof(BatchJob) * cap_tab);
+            }
+            struct G { int off, n, total, ndim, half, tile; };
+            std::vector<G> gl;
+            int off = 0;
+            for (auto& g : groups) {
+                int begin = 0;
+                for (size_t q = 0; q < g.second.size(); ++q) {
+                    host_tab[off + (int)q] = batch_forward_job(g.second[q]->bf, kBatchSteps, begin);
+                    begin += g.second[q]->bf.nblk;
+                }
+                gl.push_back({off, (int)g.second.size(), begin, std::get<0>(g.first), std::get<1>(g.first),
+                              std::get<2>(g.first)});
+                off += (int)g.second.size();
+            }
+            if (st == WF_OK)
+                st = hip_check(hipMemcpyAsync(dev_tab.ptr, host_tab, sizeof(BatchJob) * ntab,
+                                              hipMemcpyHostToDevice, s), "batch table");
+            for (int k = 0; k < kBatchSteps && st == WF_OK; ++k)
+                for (const G& g : gl)
+                    st = hip_check(launch_step_batch(dev_tab.as<BatchJob>() + g.off, g.n, g.total, g.ndim,
+                                                     g.half, g.tile, k, s), "batched step");
+            if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+            for (auto& g : groups)
+                for (EJob* j : g.second) {
+                    const int steps = std::max(0, std::min(kBatchSteps, j->bf.nt - 1 - j->bf.n));
+                    batch_forward_advance(j->bf, steps);
+                    if (st != WF_OK) j->st = st;
+                }
+        }
+        // retire finished grids
+        std::vector<EJob*> keep;
+        for (EJob* j : active) {
+            if (j->st == WF_OK && j->bf.n < j->bf.nt - 1) {
+                keep.push_back(j);
+                continue;
+            }
+            if (j->st == WF_OK && j->bf.rec) {
+                j->st = batch_forward_finish(j->bf, s);
+                if (j->st == WF_OK) j->st = hip_check(hipStreamSynchronize(s), "sync");
+            }
+            delete j->md;
+            j->md = nullptr;
+            complete(j);
+        }
+        active.swap(keep);
+    }
+    if (host_tab) (void)hipHostFree(host_tab);
+    dev_tab.reset();
+    (void)hipStreamDestroy(s);
+    set_thread_arena(nullptr);
+}
+
 extern "C" {
 
-wf_status wf_engine_create(int64_t, int, wf_engine** out) {
-    if (out) *out = nullptr;
-    return fail(WF_E_STATE, "serving engine not available in this build");
+wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** out) {
+    try {
+        if (!out) return fail(WF_E_ARG, "out is NULL");
+        *out = nullptr;
+        if (hbm_budget_bytes < ((int64_t)64 << 20)) return fail(WF_E_ARG, "budget below 64 MiB");
+        if (max_slots < 1) return fail(WF_E_ARG, "max_slots must be >= 1");
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(WF_E_HIP, "hipMemGetInfo");
+        if (hbm_budget_bytes > (int64_t)fr) return fail(WF_E_BUDGET, "budget exceeds free device memory");
+        wf_engine* e = new wf_engine();
+        e->arena = arena_create(hbm_budget_bytes);
+        if (!e->arena) {
+            delete e;
+            return WF_E_NOMEM;
+        }
+        (void)hipGetDevice(&e->device);
+        e->budget = hbm_budget_bytes;
+        e->max_slots = max_slots;
+        for (int i = 0; i < kWorkers; ++i) e->threads.emplace_back([e] { e->worker(); });
+        e->threads.emplace_back([e] { e->batcher(); });
+        *out = e;
+        return WF_OK;
+    } catch (...) {
+        return fail(WF_E_NOMEM, "engine creation failed");
+    }
 }
-wf_status wf_engine_submit(wf_engine*, const wf_request*, uint64_t*) {
-    return fail(WF_E_STATE, "serving engine not available in this build");
-}
-wf_status wf_engine_poll(wf_engine*, uint64_t*, wf_status*, int, int* n_done, int) {
-    if (n_done) *n_done = 0;
-    return fail(WF_E_STATE, "serving engine not available in this build");
-}
-wf_status wf_engine_stats(const wf_engine*, int64_t*, int64_t*, int64_t*, int64_t*) {
-    return fail(WF_E_STATE, "serving engine not available in this build");
-}
-wf_status wf_engine_destroy(wf_engine*) { return WF_OK; }
 
+wf_status wf_engine_submit(wf_engine* e, const wf_request* r, uint64_t* ticket) {
+    try {
+        if (!e || !r || !ticket) return fail(WF_E_ARG, "NULL argument");
+        wf_status st = check_geom(&r->geom);
+        if (st != WF_OK) return st;
+        if (r->kind != WF_REQ_FORWARD && r->kind != WF_REQ_GRADIENT) return fail(WF_E_ARG, "unknown request kind");
+        if (!r->m_dev) return fail(WF_E_ARG, "m is NULL");
+        if (r->nt < 1 || r->nsrc < 0 || r->nrec < 0) return fail(WF_E_ARG, "bad nt or point counts");
+        if (!(r->dt > 0.0)) return fail(WF_E_ARG, "dt must be > 0");
+        if ((r->nsrc > 0 && (!r->src_xyz || !r->src_wav)) || (r->nrec > 0 && (!r->rec_xyz)))
+            return fail(WF_E_ARG, "missing source or receiver arrays");
+        if (r->kind == WF_REQ_FORWARD && r->nrec > 0 && !r->rec_out) return fail(WF_E_ARG, "rec_out is NULL");
+        if (r->kind == WF_REQ_GRADIENT && (!r->grad_out || (r->nrec > 0 && !r->d_obs)))
+            return fail(WF_E_ARG, "gradient requests need grad_out and d_obs");
+        EJob* j = new EJob();
+        j->rq = *r;
+        const int D = r->geom.ndim;
+        if (r->nsrc > 0) j->src.assign(r->src_xyz, r->src_xyz + (size_t)r->nsrc * D);
+        if (r->nrec > 0) j->rec.assign(r->rec_xyz, r->rec_xyz + (size_t)r->nrec * D);
+        j->rq.src_xyz = nullptr;
+        j->rq.rec_xyz = nullptr;
+        st = footprint(r, e->budget, j);
+        if (st != WF_OK) {
+            delete j;
+            return st;
+        }
+        std::lock_guard<std::mutex> lk(e->mu);
+        j->ticket = e->next_ticket++;
+        *ticket = j->ticket;
+        e->pending.push_back(j);
+        e->admit();
+        return WF_OK;
+    } catch (...) {
+        return fail(WF_E_NOMEM, "submit failed");
+    }
 }
+
+wf_status wf_engine_poll(wf_engine* e, uint64_t* done_tickets, wf_status* done_status, int cap,
+                         int* n_done, int wait_ms) {
+    if (!e || !n_done || cap < 0 || (cap > 0 && (!done_tickets || !done_status)))
+        return fail(WF_E_ARG, "bad arguments");
+    std::unique_lock<std::mutex> lk(e->mu);
+    if (wait_ms > 0 && e->done.empty())
+        e->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !e->done.empty(); });
+    int n = 0;
+    while (n < cap && !e->done.empty()) {
+        done_tickets[n] = e->done.front().first;
+        done_status[n] = e->done.front().second;
+        e->done.pop_front();
+        ++n;
+    }
+    *n_done = n;
+    return WF_OK;
+}
+
+wf_status wf_engine_stats(const wf_engine* ce, int64_t* queued, int64_t* running, int64_t* completed,
+                          int64_t* bytes_in_use) {
+    if (!ce) return fail(WF_E_ARG, "engine is NULL");
+    wf_engine* e = const_cast<wf_engine*>(ce);
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (queued) *queued = (int64_t)e->pending.size();
+    if (running) *running = e->running;
+    if (completed) *completed = e->completed;
+    if (bytes_in_use) *bytes_in_use = arena_used(e->arena);
+    return WF_OK;
+}
+
+wf_status wf_engine_destroy(wf_engine* e) {
+    if (!e) return WF_OK;
+    {
+        // every submitted request runs to completion first
+        std::unique_lock<std::mutex> lk(e->mu);
+        e->cv_done.wait(lk, [&] { return e->pending.empty() && e->running == 0; });
+        e->stop = true;
+        e->cv_work.notify_all();
+    }
+    for (auto& t : e->threads) t.join();
+    arena_destroy(e->arena);
+    for (EJob* j : e->pending) delete j;
+    delete e;
+    return WF_OK;
+}
+
+}  // extern "C"

@@ -64,6 +64,25 @@ struct StepParams {
 // Largest number of injection nodes a block can stage in LDS.
 constexpr int kInjCap = 1024;
 
+// One grid of a batched step launch (see k_step_batch).
+struct BatchJob {
+    StepParams p;          // planned for this grid; cur/old/out set per step
+    float* buf0;           // u^{n0} at the first step of the launch sequence
+    float* buf1;           // u^{n0-1}
+    int64_t inj_stride;    // floats per row of the injection increments
+    int64_t smp_stride;    // floats per row of the sampled record
+    int n0;                // step index at k = 0
+    int nsteps;            // steps of this grid in the sequence
+    int block_begin;       // first block (a multiple of 8)
+    int nblk;              // blocks of this grid (sampling + stencil)
+};
+
+// Launch step k of a batch sequence over njobs grids of dimension ndim and
+// half order `half`, all planned with the same tile shape; total_blocks is the
+// end of the last job's block range.
+hipError_t launch_step_batch(const BatchJob* jobs_dev, int njobs, int total_blocks, int ndim,
+                             int half, int tile, int k, hipStream_t s);
+
 // Tile shapes (threads along z carry 4 points each).
 struct TileShape {
     int bz, by;   // threads along z and y per block
@@ -132,6 +151,11 @@ hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
 // count of non-finite values in x[0..n) added to *count
 hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count, hipStream_t s);
+// r = d - d_obs (r may alias d); partial[b] = sum over block b of r^2 in FP64,
+// for nblocks = residual_blocks(n) blocks (summed on the host in fixed order).
+int residual_blocks(int64_t n);
+hipError_t launch_residual(const float* d, const float* d_obs, float* r, int64_t n, double* partial,
+                           hipStream_t s);
 // min and max of m over n values into out[0], out[1] (out pre-filled by caller)
 hipError_t launch_minmax(const float* x, int64_t n, float* out2, hipStream_t s);
 

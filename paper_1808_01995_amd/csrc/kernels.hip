@@ -20,6 +20,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace wf {
 
@@ -95,7 +96,7 @@ __device__ __forceinline__ float update(float c, float old, float kap, float lap
 // plane in between.
 // ---------------------------------------------------------------------------
 template <bool D3, int M, int BZ, int BY, int PF, bool IMG>
-__global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
+__device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
     constexpr int NT = BZ * BY;
     constexpr int TZ = 4 * BZ;
     constexpr int P = (M + 3) & ~3;     // z halo rounded up to whole float4s
@@ -114,10 +115,10 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
     __shared__ int inj_cl[kInjCap];
     __shared__ float inj_vl[kInjCap];
 
-    if ((int)blockIdx.x < p.smp_blocks) {
+    if (bidx < p.smp_blocks) {
         // sampling role (the first blocks dispatched, spread over every XCD):
         // interpolate the current field at the receivers
-        const int i = (int)blockIdx.x * NT + (int)threadIdx.x;
+        const int i = bidx * NT + (int)threadIdx.x;
         if (i < p.smp_n) {
             float acc = 0.0f;
             for (int k = 0; k < p.smp_K; ++k)
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
         }
         return;
     }
-    const int r = xcd_remap((int)blockIdx.x - p.smp_blocks, p.nblocks);
+    const int r = xcd_remap(bidx - p.smp_blocks, p.nblocks);
     if (r >= p.nblocks) return;
     int t = r;
     const int itz = t % p.ntz;
@@ -339,6 +340,45 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
     }
 }
 
+template <bool D3, int M, int BZ, int BY, int PF, bool IMG>
+__global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
+    step_body<D3, M, BZ, BY, PF, IMG>(p, (int)blockIdx.x);
+}
+
+// Many grids of one dimension and order advanced by one step in one launch
+// (the serving engine's batch of small requests). Job j owns the blocks
+// [block_begin, block_begin + nblk), block_begin a multiple of 8 so that each
+// job's blocks keep their XCD placement; at launch step k the job advances from
+// its step n0 + k, alternating its two fields, with this step's injection and
+// sampling rows.
+template <bool D3, int M, int BZ, int BY, int PF>
+__global__ void __launch_bounds__(BZ * BY) k_step_batch(const BatchJob* __restrict__ jobs, int njobs,
+                                                        int k) {
+    int lo = 0, hi = njobs - 1;
+    const int b = (int)blockIdx.x;
+    while (lo < hi) {   // uniform binary search for the owning job
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchJob& J = jobs[lo];
+    if (k >= J.nsteps || b >= J.block_begin + J.nblk) return;
+    StepParams p = J.p;
+    const int64_t n = (int64_t)J.n0 + k;
+    if (k & 1) {
+        p.cur = J.buf1;
+        p.old = J.buf0;
+        p.out = J.buf0;
+    } else {
+        p.cur = J.buf0;
+        p.old = J.buf1;
+        p.out = J.buf1;
+    }
+    if (p.inj_blk) p.inj_inc += n * J.inj_stride;
+    if (p.smp_out) p.smp_out += n * J.smp_stride;
+    step_body<D3, M, BZ, BY, PF, false>(p, b - J.block_begin);
+}
+
 // ---------------------------------------------------------------------------
 // sparse operators and helpers
 // ---------------------------------------------------------------------------
@@ -432,6 +472,25 @@ __global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, int64
         d[i] = s[i];
 }
 
+__global__ void k_residual(const float* d, const float* __restrict__ d_obs, float* r, int64_t n,
+                           double* partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = d[i] - d_obs[i];
+        r[i] = v;
+        acc += (double)v * (double)v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 __global__ void k_count_nonfinite(const float* __restrict__ x, int64_t n, unsigned int* count) {
     unsigned int c = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -514,8 +573,10 @@ const void* step_fn(int ndim, int half, int tile, bool img) {
 
 // Resident blocks of a step kernel on the whole device (cached).
 int step_capacity(int ndim, int half, int tile, bool img) {
+    static std::mutex mu;
     static int cache[2][kMaxHalf + 1][2][2] = {};
     static int cus = 0;
+    std::lock_guard<std::mutex> lk(mu);
     int& c = cache[ndim - 2][half][tile][img ? 1 : 0];
     if (c > 0) return c;
     if (cus == 0) {
@@ -608,6 +669,38 @@ hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hi
     return hipLaunchKernel(fn, dim3(grid), dim3(ts.bz * ts.by), args, 0, s);
 }
 
+template <int M>
+hipError_t launch_batch_m(const BatchJob* jobs, int njobs, int total, int ndim, int tile, int k,
+                          hipStream_t s) {
+    constexpr int PF = M <= 4 ? WF_PF_LO : WF_PF_HI;
+    if (ndim == 2) {
+        hipLaunchKernelGGL((k_step_batch<false, M, kTile2.bz, kTile2.by, PF>), dim3(total),
+                           dim3(kTile2.bz * kTile2.by), 0, s, jobs, njobs, k);
+    } else if (tile == 0) {
+        hipLaunchKernelGGL((k_step_batch<true, M, kTiles3[0].bz, kTiles3[0].by, PF>), dim3(total),
+                           dim3(kTiles3[0].bz * kTiles3[0].by), 0, s, jobs, njobs, k);
+    } else {
+        hipLaunchKernelGGL((k_step_batch<true, M, kTiles3[1].bz, kTiles3[1].by, PF>), dim3(total),
+                           dim3(kTiles3[1].bz * kTiles3[1].by), 0, s, jobs, njobs, k);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(const BatchJob* jobs, int njobs, int total, int ndim, int half, int tile,
+                             int k, hipStream_t s) {
+    if (njobs <= 0 || total <= 0) return hipSuccess;
+    switch (half) {
+        case 2: return launch_batch_m<2>(jobs, njobs, total, ndim, tile, k, s);
+        case 3: return launch_batch_m<3>(jobs, njobs, total, ndim, tile, k, s);
+        case 4: return launch_batch_m<4>(jobs, njobs, total, ndim, tile, k, s);
+        case 5: return launch_batch_m<5>(jobs, njobs, total, ndim, tile, k, s);
+        case 6: return launch_batch_m<6>(jobs, njobs, total, ndim, tile, k, s);
+        case 7: return launch_batch_m<7>(jobs, njobs, total, ndim, tile, k, s);
+        case 8: return launch_batch_m<8>(jobs, njobs, total, ndim, tile, k, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_inject(const InjectParams& p, hipStream_t s) {
     if (p.nnodes <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_inject, dim3((p.nnodes + 255) / 256), dim3(256), 0, s, p);
@@ -659,6 +752,14 @@ hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s) {
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy, dim3(grid_1d(n / 4 + 1, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+int residual_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024)); }
+
+hipError_t launch_residual(const float* d, const float* d_obs, float* r, int64_t n, double* partial,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_residual, dim3(residual_blocks(n)), dim3(256), 0, s, d, d_obs, r, n, partial);
     return hipGetLastError();
 }
 

@@ -250,9 +250,7 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
     // memory plan: adjoint pair + gradient accumulator (3 fields) plus either
     // every forward field (store-all: nt fields incl. one zero field) or a
     // revolve pool of 2 s + 3 fields
-    size_t free_b = 0, total_b = 0;
-    WF_TRY(hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo"));
-    int64_t cap = (int64_t)free_b - ((int64_t)256 << 20);
+    int64_t cap = device_free_bytes();
     if (budget > 0) cap = std::min<int64_t>(cap, budget);
     const int64_t fixed = 3 * fb;
     bool store_all = false;
@@ -366,6 +364,67 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
     WF_TRY(hip_check(launch_unpitch(G, grad_out, L.nx, L.ny, L.nz, L.sx, L.sy, s), "unpitch"));
     // the pools are freed when this returns; wait for the work that reads them
     return hip_check(hipStreamSynchronize(s), "sync");
+}
+
+// ---------------------------------------------------------------------------
+// batched forward shots
+// ---------------------------------------------------------------------------
+wf_status batch_forward_begin(Model& md, double dt, int nt, const PointSet& src, const float* wav,
+                              const PointSet& rec, float* rec_out, hipStream_t s, BatchFwd& b) {
+    const Layout& L = md.L;
+    WF_TRY(md.ensure_kap(dt, s));
+    b = BatchFwd();
+    b.md = &md;
+    b.src = &src;
+    b.rec = &rec;
+    b.nt = nt;
+    b.rec_out = rec_out;
+    b.A = md.u(0);
+    b.B = md.u(1);
+    WF_TRY(hip_check(launch_fill(b.A, L.elems, 0.0f, s), "fill"));
+    WF_TRY(hip_check(launch_fill(b.B, L.elems, 0.0f, s), "fill"));
+    StepParams& p = b.p;
+    md.fill_step(p, dt);
+    // many grids share each launch, so each grid uses long x-chunks (little
+    // warm-up re-reading) instead of spreading itself over the whole device
+    const int cx = std::min(L.nx, std::max(48, 8 * md.half));
+    step_plan(p, md.geom.ndim, md.half, false, cx, p.tile, 0);
+    const int NT = block_threads(md, p);
+    Injector inj;
+    WF_TRY(inj.prepare(md, src, p, wav, nt, md.d_inc[0], s));
+    if (src.nnodes > 0 && !inj.fz) return fail(WF_E_STATE, "sources cannot be injected by the batched kernel");
+    inj.configure(p, 0);
+    b.inj_stride = inj.fz ? inj.fz->nnodes : 0;
+    set_sampling(p, &rec, rec.npts ? rec_out : nullptr, NT);
+    p.smp_blocks = (p.smp_blocks + 7) / 8 * 8;   // keep the stencil blocks XCD-aligned
+    b.nblk = p.smp_blocks + (p.nblocks + 7) / 8 * 8;
+    if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, s), "fill"));
+    return WF_OK;
+}
+
+BatchJob batch_forward_job(const BatchFwd& b, int k_steps, int block_begin) {
+    BatchJob j;
+    j.p = b.p;
+    j.buf0 = b.A;
+    j.buf1 = b.B;
+    j.inj_stride = b.inj_stride;
+    j.smp_stride = b.rec ? b.rec->npts : 0;
+    j.n0 = b.n;
+    j.nsteps = std::max(0, std::min(k_steps, b.nt - 1 - b.n));
+    j.block_begin = block_begin;
+    j.nblk = b.nblk;
+    return j;
+}
+
+void batch_forward_advance(BatchFwd& b, int steps) {
+    b.n += steps;
+    if (steps & 1) std::swap(b.A, b.B);
+}
+
+wf_status batch_forward_finish(BatchFwd& b, hipStream_t s) {
+    if (b.nt > 1 && b.rec && b.rec->npts > 0)
+        WF_TRY(sample(*b.rec, b.A, b.rec_out + (int64_t)(b.nt - 1) * b.rec->npts, s));
+    return WF_OK;
 }
 
 }  // namespace wf

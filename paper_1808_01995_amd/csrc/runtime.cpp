@@ -121,15 +121,40 @@ std::vector<float> eta_profile(const wf_geom* g, int axis) {
 // ---------------------------------------------------------------------------
 // device memory helpers
 // ---------------------------------------------------------------------------
+static thread_local Arena* t_arena = nullptr;
+void set_thread_arena(Arena* a) { t_arena = a; }
+
+int64_t device_free_bytes() {
+    if (t_arena) return arena_largest_free(t_arena);
+    size_t f = 0, t = 0;
+    if (hipMemGetInfo(&f, &t) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (int64_t)f - ((int64_t)256 << 20);   // headroom for the runtime
+}
+
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset() {
-    if (ptr) hipFree(ptr);
+    if (ptr) {
+        if (arena) arena_free(arena, ptr);
+        else hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
+    arena = nullptr;
 }
 wf_status DevBuf::alloc(int64_t nbytes) {
     reset();
     if (nbytes <= 0) return WF_OK;
+    if (t_arena) {
+        void* q = arena_alloc(t_arena, nbytes);
+        if (!q) return fail(WF_E_BUDGET, "device arena exhausted (%lld bytes requested)", (long long)nbytes);
+        ptr = q;
+        bytes = nbytes;
+        arena = t_arena;
+        return WF_OK;
+    }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, (size_t)nbytes);
     if (e != hipSuccess) {
@@ -411,6 +436,7 @@ wf_status Model::init(const wf_geom* g, const float* m_dev, hipStream_t s) {
 
 wf_status Model::set_m(const float* m_dev, hipStream_t s) {
     if (!m_dev) return fail(WF_E_ARG, "m is NULL");
+    last_stream = s;
     wf_status st;
     if ((st = hip_check(hipMemcpyAsync(d_m.f(), m_dev, (size_t)L.npoints * 4,
                                        hipMemcpyDeviceToDevice, s), "copy m")) != WF_OK)
@@ -439,6 +465,7 @@ wf_status Model::set_m(const float* m_dev, hipStream_t s) {
 double Model::vmax() const { return 1.0 / std::sqrt(m_min); }
 
 wf_status Model::ensure_kap(double dt, hipStream_t s) {
+    last_stream = s;
     if (dt == kap_dt) return WF_OK;
     wf_status st = hip_check(launch_coef(d_m.f(), kap(), L.nx, L.ny, L.nz, L.sx, L.sy, dt, s), "coef");
     if (st != WF_OK) return st;
@@ -479,7 +506,7 @@ wf_status Model::points(int npts, const double* xyz, const PointSet** out) {
         size_t lru = 0;
         for (size_t i = 1; i < pcache.size(); ++i)
             if (pcache[i].tick < pcache[lru].tick) lru = i;
-        (void)hipDeviceSynchronize();
+        (void)hipStreamSynchronize(last_stream);
         delete pcache[lru].ps;
         pcache.erase(pcache.begin() + (long)lru);
     }
@@ -494,7 +521,7 @@ wf_status Model::points(int npts, const double* xyz, const PointSet** out) {
 }
 
 Model::~Model() {
-    (void)hipDeviceSynchronize();
+    (void)hipStreamSynchronize(last_stream);
     for (auto& c : pcache) delete c.ps;
 }
 

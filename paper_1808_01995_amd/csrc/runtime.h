@@ -24,10 +24,24 @@ void comp_shape(const wf_geom* g, int64_t* nx, int64_t* ny, int64_t* nz);
 double critical_dt(const wf_geom* g, double vmax);
 std::vector<float> eta_profile(const wf_geom* g, int axis);
 
+// Sub-allocator over one device allocation (the serving engine's HBM budget):
+// first fit with coalescing, 256-byte granularity, thread-safe.
+struct Arena;
+Arena* arena_create(int64_t bytes);          // nullptr on failure (message set)
+void arena_destroy(Arena* a);
+void* arena_alloc(Arena* a, int64_t bytes);   // nullptr when it does not fit
+void arena_free(Arena* a, void* p);
+int64_t arena_used(const Arena* a);
+int64_t arena_largest_free(Arena* a);
+// While set on a thread, DevBuf allocations made by that thread come from the
+// arena (and are returned to it when freed, from any thread).
+void set_thread_arena(Arena* a);
+
 // Owned device allocation.
 struct DevBuf {
     void* ptr = nullptr;
     int64_t bytes = 0;
+    Arena* arena = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -109,6 +123,7 @@ struct Model : public wf_model {
     double kap_dt = -1.0;
     std::vector<PCache> pcache;
     uint64_t tick = 0;
+    hipStream_t last_stream = nullptr;   // the stream of the most recent work
 
     ~Model() override;
     wf_status init(const wf_geom* g, const float* m_dev, hipStream_t s);
@@ -147,6 +162,31 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
 wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                        const PointSet& rec, const float* residual, float* grad_out, int n_ck,
                        int64_t budget, hipStream_t s);
+
+// Batched forward shots (serving engine): a grid advanced by k_step_batch
+// launches shared with other grids. begin() prepares fields, coefficients,
+// injection increments and the launch plan; job() describes the next k steps;
+// advance() moves the state on; finish() writes the last record row.
+struct BatchFwd {
+    Model* md = nullptr;
+    const PointSet* src = nullptr;
+    const PointSet* rec = nullptr;
+    StepParams p{};
+    float* A = nullptr;    // u^n
+    float* B = nullptr;    // u^{n-1}
+    int n = 0, nt = 0;
+    int64_t inj_stride = 0;
+    float* rec_out = nullptr;
+    int nblk = 0;          // blocks of one step (sampling + stencil, multiples of 8)
+};
+wf_status batch_forward_begin(Model& md, double dt, int nt, const PointSet& src, const float* wav,
+                              const PointSet& rec, float* rec_out, hipStream_t s, BatchFwd& b);
+BatchJob batch_forward_job(const BatchFwd& b, int k_steps, int block_begin);
+void batch_forward_advance(BatchFwd& b, int steps);
+wf_status batch_forward_finish(BatchFwd& b, hipStream_t s);
+
+// Free device memory the current thread may allocate (its arena, if any).
+int64_t device_free_bytes();
 
 // Revolve schedule (revolve.cpp).
 int64_t revolve_cost(int64_t steps, int snaps);

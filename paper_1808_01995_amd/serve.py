@@ -1,0 +1,215 @@
+"""Serving front-end over the library's continuous-batching engine.
+
+`Server` submits shot-modelling and gradient requests to the native engine
+(wf_engine_*), which admits them by HBM budget, batches small grids into
+shared launches and runs the rest concurrently; the front-end only keeps the
+request tensors alive, timestamps arrivals and completions, and reports
+latency percentiles and throughput.
+
+`build_request` turns a request description (dimension, grid size, space
+order, steps, kind, seed) into device tensors: a smooth random velocity model,
+a 10 Hz Ricker source at the centre at 20 m depth, receivers at 20 m depth
+(a line in 2D, 64 x 64 in 3D); gradient requests carry observed data modelled
+on a model perturbed by a few percent.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from .propagator import Propagator, slowness_sq
+
+
+@dataclasses.dataclass
+class Request:
+    kind: int                      # _abi.WF_REQ_FORWARD or _abi.WF_REQ_GRADIENT
+    geom: _abi.wf_geom
+    m: torch.Tensor                # computational-grid squared slowness (device)
+    dt: float
+    nt: int
+    src_xyz: np.ndarray
+    src_wav: torch.Tensor
+    rec_xyz: np.ndarray
+    rec_out: torch.Tensor
+    d_obs: Optional[torch.Tensor] = None
+    grad_out: Optional[torch.Tensor] = None
+    misfit: Optional[float] = None
+    arrival: float = 0.0           # seconds (wall clock) when the request arrived
+    done: float = 0.0
+    status: int = 0
+    tag: Dict = dataclasses.field(default_factory=dict)
+    _misfit_buf: Optional[ctypes.c_double] = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+    @property
+    def updates(self) -> int:
+        n = 1
+        for a in range(self.geom.ndim):
+            n *= self.geom.n[a] + 2 * self.geom.nbl
+        return n * (self.nt - 1) * (3 if self.kind == _abi.WF_REQ_GRADIENT else 1)
+
+
+def build_request(spec: Dict, device="cuda", vmin: float = 1.5, vmax: float = 4.5,
+                  h: float = 10.0, nbl: int = 40, f0_hz: float = 10.0) -> Request:
+    """Device tensors for one serving request (see module docstring)."""
+    from synthetic import grid_receivers, line_receivers, ricker, smooth_random_velocity
+    nd, n, so, steps = spec["ndim"], spec["n"], spec["space_order"], spec["steps"]
+    shape = (n,) * nd
+    v = smooth_random_velocity(shape, spec["seed"], sigma=max(2.0, n / 32.0), vmin=vmin, vmax=vmax)
+    ext = (n - 1) * h
+    if nd == 2:
+        src = np.array([[ext / 2, 20.0]])
+        rec = line_receivers(n, 0.0, ext, 20.0, ndim=2)
+    else:
+        src = np.array([[ext / 2, ext / 2, 20.0]])
+        rec = grid_receivers(64, 64, ext, ext, 20.0)
+    geom = _abi.make_geom(shape, (h,) * nd, nbl, so, float(v.max()))
+    m = slowness_sq(v, nbl, device)
+    nt = steps + 1
+    dt = 0.5 * _abi.wf_critical_dt(geom, float(v.max()) * 1.06)
+    wav = torch.from_numpy(ricker(nt, dt, f0_hz)[:, None].astype(np.float32)).to(device)
+    rec_out = torch.empty((nt, rec.shape[0]), dtype=torch.float32, device=device)
+    kind = _abi.WF_REQ_FORWARD if spec["kind"] == "forward" else _abi.WF_REQ_GRADIENT
+    r = Request(kind, geom, m, dt, nt, src, wav, rec, rec_out, tag=dict(spec))
+    if kind == _abi.WF_REQ_GRADIENT:
+        # observed data from the model perturbed by `perturb` (smoothly)
+        pattern = smooth_random_velocity(shape, spec["seed"] + 7, sigma=max(2.0, n / 16.0),
+                                         vmin=-1.0, vmax=1.0)
+        v_true = v * (1.0 + spec.get("perturb", 0.05) * pattern)
+        prop = Propagator(v_true, spacing=(h,) * nd, nbl=nbl, space_order=so, c_ref=float(v.max()))
+        r.d_obs = prop.forward(dt, nt, src, wav, rec)
+        torch.cuda.synchronize()
+        prop.close()
+        r.grad_out = torch.empty(m.shape, dtype=torch.float32, device=device)
+        r._misfit_buf = ctypes.c_double(0.0)
+    return r
+
+
+class Server:
+    """Client of one native engine (HBM budget, slot limit)."""
+
+    def __init__(self, hbm_budget_bytes: Optional[int] = None, max_slots: int = 64,
+                 budget_fraction: float = 0.9):
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget_bytes = int(budget_fraction * free)
+        self.budget = int(hbm_budget_bytes)
+        self.handle = _abi.wf_engine_create(self.budget, max_slots)
+        self.inflight: Dict[int, Request] = {}
+        self.completed: List[Request] = []
+
+    def submit(self, r: Request) -> int:
+        torch.cuda.synchronize()   # the request's inputs are complete before the engine reads them
+        q = _abi.wf_request()
+        q.kind = r.kind
+        q.geom = r.geom
+        q.m_dev = r.m.data_ptr()
+        q.dt = r.dt
+        q.nt = r.nt
+        r._src = np.ascontiguousarray(r.src_xyz, dtype=np.float64)
+        r._rec = np.ascontiguousarray(r.rec_xyz, dtype=np.float64)
+        q.nsrc = r._src.shape[0]
+        q.src_xyz = r._src.ctypes.data
+        q.src_wav = r.src_wav.data_ptr()
+        q.nrec = r._rec.shape[0]
+        q.rec_xyz = r._rec.ctypes.data
+        q.rec_out = r.rec_out.data_ptr()
+        if r.kind == _abi.WF_REQ_GRADIENT:
+            q.d_obs = r.d_obs.data_ptr()
+            q.grad_out = r.grad_out.data_ptr()
+            q.misfit_out = ctypes.addressof(r._misfit_buf)
+        if not r.arrival:
+            r.arrival = time.perf_counter()
+        t = _abi.wf_engine_submit(self.handle, q)
+        self.inflight[t] = r
+        return t
+
+    def poll(self, wait_ms: int = 0) -> List[Request]:
+        out = []
+        for t, st in _abi.wf_engine_poll(self.handle, 256, wait_ms):
+            r = self.inflight.pop(t)
+            r.done = time.perf_counter()
+            r.status = st
+            if r._misfit_buf is not None:
+                r.misfit = r._misfit_buf.value
+            out.append(r)
+        self.completed.extend(out)
+        return out
+
+    def stats(self):
+        return _abi.wf_engine_stats(self.handle)
+
+    def drain(self):
+        while self.inflight:
+            self.poll(wait_ms=50)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.drain()
+            _abi.wf_engine_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_stream(server: Server, requests: List[Request], arrivals: Optional[List[float]] = None) -> Dict:
+    """Submit `requests` at the given arrival offsets (seconds from now; all at
+    once if None), wait for all, and return throughput and latency figures."""
+    t0 = time.perf_counter()
+    order = sorted(range(len(requests)), key=lambda i: (arrivals[i] if arrivals else 0.0))
+    k = 0
+    while k < len(order) or server.inflight:
+        now = time.perf_counter() - t0
+        while k < len(order) and (arrivals is None or arrivals[order[k]] <= now):
+            r = requests[order[k]]
+            r.arrival = t0 + (arrivals[order[k]] if arrivals else 0.0)
+            server.submit(r)
+            k += 1
+        wait = 1
+        if k < len(order) and arrivals is not None:
+            wait = max(1, min(20, int(1000 * (arrivals[order[k]] - (time.perf_counter() - t0)))))
+        server.poll(wait_ms=wait if server.inflight else 0)
+        if not server.inflight and k < len(order) and arrivals is not None:
+            time.sleep(max(0.0, arrivals[order[k]] - (time.perf_counter() - t0)))
+    t1 = time.perf_counter()
+    lat = np.array([r.latency for r in requests])
+    bad = [r for r in requests if r.status != 0]
+    return {"requests": len(requests), "makespan_s": t1 - t0, "shots_per_s": len(requests) / (t1 - t0),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "failed": len(bad)}
+
+
+def run_one_shot_baseline(requests: List[Request]) -> Dict:
+    """The plain propagator, one request at a time (model created per request,
+    one kernel launch per time step): the reference throughput mu_0."""
+    t0 = time.perf_counter()
+    outs = []
+    for r in requests:
+        nd = r.geom.ndim
+        shape = tuple(r.geom.n[a] for a in range(nd))
+        prop = Propagator(m=r.m, shape=shape, spacing=tuple(r.geom.h[a] for a in range(nd)),
+                          nbl=r.geom.nbl, space_order=r.geom.space_order, c_ref=r.geom.c_ref)
+        d = prop.forward(r.dt, r.nt, r.src_xyz, r.src_wav, r.rec_xyz)
+        if r.kind == _abi.WF_REQ_GRADIENT:
+            g = prop.gradient(r.dt, r.nt, r.src_xyz, r.src_wav, r.rec_xyz, (d - r.d_obs).contiguous())
+            outs.append((d, g))
+        else:
+            outs.append((d, None))
+        torch.cuda.synchronize()
+        prop.close()
+    t1 = time.perf_counter()
+    return {"requests": len(requests), "seconds": t1 - t0, "shots_per_s": len(requests) / (t1 - t0),
+            "outputs": outs}

@@ -1,0 +1,140 @@
+"""Serving engine (continuous batching): every result is the same alone and
+in the mix (bitwise), matches the plain propagator and the oracle, admission
+never exceeds the HBM budget, requests arriving while others run are admitted
+and overlap, and an invalid request is rejected without disturbing the rest."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _specs():
+    return [
+        {"ndim": 2, "n": 120, "space_order": 4, "steps": 150, "kind": "forward", "seed": 11},
+        {"ndim": 2, "n": 200, "space_order": 8, "steps": 90, "kind": "forward", "seed": 12},
+        {"ndim": 2, "n": 96, "space_order": 12, "steps": 220, "kind": "forward", "seed": 13},
+        {"ndim": 3, "n": 40, "space_order": 8, "steps": 70, "kind": "forward", "seed": 14},
+        {"ndim": 2, "n": 80, "space_order": 8, "steps": 60, "kind": "gradient", "seed": 15, "perturb": 0.05},
+        {"ndim": 3, "n": 30, "space_order": 4, "steps": 45, "kind": "gradient", "seed": 16, "perturb": 0.05},
+    ]
+
+
+def _build(specs, nbl=12):
+    from paper_1808_01995_amd.serve import build_request
+    return [build_request(s, nbl=nbl) for s in specs]
+
+
+def _results(reqs):
+    out = []
+    for r in reqs:
+        out.append((r.rec_out.clone(), None if r.grad_out is None else r.grad_out.clone(), r.misfit))
+    return out
+
+
+def test_mix_equals_alone_and_plain_propagator():
+    from paper_1808_01995_amd.serve import Server, run_one_shot_baseline, run_stream
+    reqs = _build(_specs())
+    srv = Server(hbm_budget_bytes=2 << 30, max_slots=16)
+    st = run_stream(srv, reqs)
+    assert st["failed"] == 0
+    mixed = _results(reqs)
+    # each alone
+    for i, r in enumerate(reqs):
+        r.rec_out.zero_()
+        if r.grad_out is not None:
+            r.grad_out.zero_()
+        run_stream(srv, [r])
+        assert r.status == 0
+        d, g, phi = _results([r])[0]
+        assert torch.equal(d, mixed[i][0]), i
+        if g is not None:
+            assert torch.equal(g, mixed[i][1]), i
+            assert phi == mixed[i][2]
+    srv.close()
+    # the plain propagator, one shot at a time
+    base = run_one_shot_baseline(reqs)
+    for i, (d, g) in enumerate(base["outputs"]):
+        rel = float((d - mixed[i][0]).norm() / d.norm())
+        assert rel <= 1e-6, (i, rel)
+        if g is not None:
+            relg = float((g - mixed[i][1]).norm() / g.norm())
+            assert relg <= 1e-5, (i, relg)
+
+
+def test_small_request_matches_oracle():
+    import oracle
+    from paper_1808_01995_amd.serve import Server, build_request, run_stream
+    spec = {"ndim": 2, "n": 70, "space_order": 8, "steps": 120, "kind": "forward", "seed": 21}
+    r = build_request(spec, nbl=10)
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    run_stream(srv, [r])
+    srv.close()
+    g = r.geom
+    shape = (g.n[0] + 2 * g.nbl, g.n[1] + 2 * g.nbl)
+    m = r.m.cpu().numpy().astype(np.float64)
+    og = oracle.Grid(shape, (g.h[0], g.h[1]), g.space_order)
+    eta = oracle.damping_eta((g.n[0], g.n[1]), g.nbl, (g.h[0], g.h[1]), g.c_ref)
+    ps = oracle.sparse_points(r.src_xyz, (g.h[0], g.h[1]), g.nbl, shape)
+    pr = oracle.sparse_points(r.rec_xyz, (g.h[0], g.h[1]), g.nbl, shape)
+    d_ref = oracle.forward(og, m, eta, r.dt, r.nt, ps, r.src_wav.cpu().numpy().astype(np.float64), pr)
+    d = r.rec_out.cpu().numpy()
+    assert np.linalg.norm(d - d_ref) / np.linalg.norm(d_ref) <= 1e-4
+
+
+def test_budget_admission_and_overlap():
+    from paper_1808_01995_amd.serve import Server, run_stream
+    specs = [{"ndim": 2, "n": 300, "space_order": 8, "steps": 400, "kind": "forward", "seed": 30 + i}
+             for i in range(8)]
+    reqs = _build(specs, nbl=20)
+    # a budget that holds only a few of these at once
+    budget = 96 << 20
+    srv = Server(hbm_budget_bytes=budget, max_slots=64)
+    peak = 0
+    for r in reqs:
+        srv.submit(r)
+    while srv.inflight:
+        srv.poll(wait_ms=2)
+        s = srv.stats()
+        peak = max(peak, s["bytes_in_use"])
+        assert s["bytes_in_use"] <= budget
+    assert all(r.status == 0 for r in reqs)
+    # a short request arriving while a long one runs finishes first
+    long_r = _build([{"ndim": 2, "n": 400, "space_order": 8, "steps": 1500, "kind": "forward", "seed": 40}],
+                    nbl=20)[0]
+    short_r = _build([{"ndim": 2, "n": 100, "space_order": 4, "steps": 60, "kind": "forward", "seed": 41}],
+                     nbl=20)[0]
+    srv.submit(long_r)
+    time.sleep(0.02)
+    srv.submit(short_r)
+    srv.drain()
+    assert short_r.done < long_r.done
+    srv.close()
+    assert peak > 0
+
+
+def test_invalid_request_rejected_without_disturbing():
+    from paper_1808_01995_amd import WaveFDError, _abi
+    from paper_1808_01995_amd.serve import Server
+    reqs = _build(_specs()[:3])
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=8)
+    t = [srv.submit(r) for r in reqs[:2]]
+    bad = reqs[2]
+    bad.geom.space_order = 5
+    with pytest.raises(WaveFDError) as e:
+        srv.submit(bad)
+    assert e.value.status == _abi.WF_E_ARG
+    srv.inflight.pop(None, None)
+    huge = _build([{"ndim": 2, "n": 100, "space_order": 4, "steps": 20, "kind": "forward", "seed": 50}])[0]
+    srv2 = Server(hbm_budget_bytes=64 << 20, max_slots=2)
+    huge.geom.n[0] = 20000
+    huge.geom.n[1] = 20000
+    with pytest.raises(WaveFDError) as e:
+        srv2.submit(huge)
+    assert e.value.status == _abi.WF_E_BUDGET
+    srv2.close()
+    srv.drain()
+    assert all(r.status == 0 for r in reqs[:2])
+    srv.close()
