@@ -94,6 +94,134 @@ def cpu_baseline(c, v, dt, sample_steps: int):
                       % (sample_steps, c.steps, "x".join(map(str, m.shape)), el)}
 
 
+def _timed(torch, fn, reps=1):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps, out
+
+
+def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
+    """512^3 physical (592^3 computational), two-layer 1.5/2.5 km/s, one
+    shot per order: GPts/s and the step kernel's algorithmic bandwidth."""
+    from paper_1808_01995_amd import Propagator, _abi
+    from synthetic import config, ricker
+    res = []
+    v = None
+    for so in orders:
+        c = config("c3_sweep", space_order=so, steps=steps)
+        if v is None:
+            v = c.velocity()
+        prop = Propagator(v, spacing=c.spacing, nbl=c.nbl, space_order=so)
+        dt = 0.5 * prop.critical_dt()
+        q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+        rec = torch.empty((c.nt, c.rec.shape[0]), device="cuda")
+        prop.forward(dt, 21, c.src, q[:21].contiguous(), c.rec, rec_out=rec[:21])   # warm-up
+        _abi.wf_profile_read(0, reset=True)
+        _abi.wf_profile_enable(True)
+        el, _ = _timed(torch, lambda: prop.forward(dt, c.nt, c.src, q, c.rec, rec_out=rec))
+        _abi.wf_profile_enable(False)
+        ms, n = _abi.wf_profile_read(0, reset=True)
+        us = ms / max(n, 1) * 1e3
+        gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
+        res.append({"space_order": so, "dt_ms": round(dt, 4), "gpts": round(prop.npoints * c.steps / el / 1e9, 1),
+                    "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs), "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3)})
+        prop.close()
+        log("c3 so%d: %s" % (so, res[-1]))
+    return {"workload": "592^3 computational (512^3 + 40-node layer), two-layer 1.5/2.5 km/s, %d updates" % steps,
+            "orders": res}
+
+
+def gradient_c4(torch, steps=2000, snaps=(-1, 50, 20)):
+    """200^3 physical (280^3), order 8, Gaussian anomaly; residual of the
+    background model against data of the true model; gradient with store-all
+    and revolve checkpointing, and through torch.autograd."""
+    from paper_1808_01995_amd import Propagator, model_data, pad_replicate, slowness_sq
+    from synthetic import config, ricker
+    c = config("c4_gradient", steps=steps)
+    v_true = c.velocity()
+    v0 = np.full(c.shape, 2.0)
+    pt = Propagator(v_true, spacing=c.spacing, nbl=c.nbl, space_order=8, c_ref=2.5)
+    dt = 0.5 * pt.critical_dt(2.5)
+    q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    d_obs = pt.forward(dt, c.nt, c.src, q, c.rec)
+    pt.close()
+    p0 = Propagator(v0, spacing=c.spacing, nbl=c.nbl, space_order=8, c_ref=2.5)
+    t_fwd, d = _timed(torch, lambda: p0.forward(dt, c.nt, c.src, q, c.rec))
+    r = (d - d_obs).contiguous()
+    out = {"workload": "280^3 computational, order 8, %d updates, 1 source, 100x100 receivers" % steps,
+           "forward_s": round(t_fwd, 3), "misfit": 0.5 * float((r.double() ** 2).sum())}
+    ref = None
+    runs = []
+    for s in snaps:
+        el, g = _timed(torch, lambda: p0.gradient(dt, c.nt, c.src, q, c.rec, r, n_checkpoints=s))
+        from paper_1808_01995_amd import _abi
+        fwd_steps = (c.nt - 1) if s == -1 else 1 + _abi.wf_revolve_forward_steps(c.nt - 1, s)
+        runs.append({"checkpoints": "all" if s == -1 else s, "seconds": round(el, 3),
+                     "forward_recompute_steps": fwd_steps,
+                     "gpts_effective": round(p0.npoints * c.steps / el / 1e9, 1)})
+        if ref is None:
+            ref = g
+        runs[-1]["bitwise_equal_to_store_all"] = bool(torch.equal(g, ref))
+        log("c4 gradient s=%s: %s" % (s, runs[-1]))
+        del g
+    out["gradient"] = runs
+    # torch.autograd path on the physical grid (replicate-pad adjoint folds the layer)
+    m_phys = torch.from_numpy((1.0 / v0 ** 2).astype(np.float32)).cuda().requires_grad_(True)
+    def ag():
+        dd = model_data(pad_replicate(m_phys, c.nbl), p0, dt, c.nt, c.src, q, c.rec, 50)
+        loss = 0.5 * ((dd - d_obs) ** 2).sum()
+        loss.backward()
+        return loss
+    el, _ = _timed(torch, ag)
+    out["autograd_forward_plus_backward_s"] = round(el, 3)
+    p0.close()
+    return out
+
+
+def serving_c5(torch, n_requests=48, scale_down=2, max_steps=1000, seed=5):
+    """Reduced serving stream (grid sizes divided by `scale_down`, steps capped):
+    one-shot-per-launch baseline mu_0, saturated throughput, Poisson arrivals."""
+    from paper_1808_01995_amd.serve import Server, build_request, run_one_shot_baseline, run_stream
+    from synthetic import serving_requests
+    specs = serving_requests(n_requests, seed=seed, scale_down=scale_down, max_steps=max_steps)
+    reqs = [build_request(sp) for sp in specs]
+    torch.cuda.synchronize()
+    base = run_one_shot_baseline(reqs)
+    mu0 = base["shots_per_s"]
+    srv = Server(max_slots=64)
+    sat = run_stream(srv, reqs)
+    rel = 0.0
+    for r, (d, g) in zip(reqs, base["outputs"]):
+        rel = max(rel, float((r.rec_out - d).norm() / max(float(d.norm()), 1e-30)))
+        if g is not None:
+            rel = max(rel, float((r.grad_out - g).norm() / max(float(g.norm()), 1e-30)))
+    base = None
+    rng = np.random.default_rng(seed)
+    poisson = []
+    for f in (0.5, 0.8, 1.2):
+        lam = f * mu0
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs))).tolist()
+        st = run_stream(srv, reqs, arr)
+        poisson.append({"lambda_over_mu0": f, "arrival_rate_per_s": round(lam, 2),
+                        "p50_ms": round(st["p50_ms"], 1), "p99_ms": round(st["p99_ms"], 1),
+                        "shots_per_s": round(st["shots_per_s"], 2), "failed": st["failed"]})
+        log("serving poisson %.1f: %s" % (f, poisson[-1]))
+    srv.close()
+    n2 = sum(1 for s_ in specs if s_["ndim"] == 2)
+    ng = sum(1 for s_ in specs if s_["kind"] == "gradient")
+    return {"workload": "%d requests (%d 2D / %d 3D, %d gradients), grid sizes / %d, <= %d steps, orders 4/8/12"
+                        % (len(specs), n2, len(specs) - n2, ng, scale_down, max_steps),
+            "one_shot_baseline_shots_per_s": round(mu0, 2),
+            "saturated": {"shots_per_s": round(sat["shots_per_s"], 2), "p50_ms": round(sat["p50_ms"], 1),
+                          "p99_ms": round(sat["p99_ms"], 1), "failed": sat["failed"]},
+            "speedup_vs_one_shot": round(sat["shots_per_s"] / mu0, 2),
+            "poisson": poisson,
+            "max_rel_l2_vs_one_shot": rel}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +230,9 @@ def main():
     ap.add_argument("--space-order", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=300)
-    ap.add_argument("--extras", action="store_true", help="also time adjoint and gradient")
+    ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
+    ap.add_argument("--rows", default="",
+                    help="comma list of further rows to measure: c3,c4,serve (or all)")
     ap.add_argument("--updates", type=int, default=None,
                     help="shorter shots (profiling runs only; the benchmark uses 1000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -199,6 +329,15 @@ def main():
         out["adjoint_gpts"] = round(updates / (time.perf_counter() - t) / 1e9, 3)
 
     prop.close()
+    rows = set(x for x in args.rows.split(",") if x)
+    if "all" in rows:
+        rows = {"c3", "c4", "serve"}
+    if "c3" in rows:
+        out["c3_sweep"] = sweep_c3(torch)
+    if "c4" in rows:
+        out["c4_gradient"] = gradient_c4(torch)
+    if "serve" in rows:
+        out["c5_serving"] = serving_c5(torch)
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(c, v, dt, args.cpu_steps)

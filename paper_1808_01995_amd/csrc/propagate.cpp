@@ -385,9 +385,12 @@ wf_status batch_forward_begin(Model& md, double dt, int nt, const PointSet& src,
     WF_TRY(hip_check(launch_fill(b.B, L.elems, 0.0f, s), "fill"));
     StepParams& p = b.p;
     md.fill_step(p, dt);
-    // many grids share each launch, so each grid uses long x-chunks (little
-    // warm-up re-reading) instead of spreading itself over the whole device
-    const int cx = std::min(L.nx, std::max(48, 8 * md.half));
+    // many grids share each launch, so a grid does not need to spread itself
+    // over the whole device; the chunk length trades warm-up re-reads against
+    // the sequential per-plane latency of each block (measured on a mixed
+    // stream of orders 4/8/12: 8 planes best in 2D, 16 in 3D)
+    int cx = std::min(L.nx, md.geom.ndim == 2 ? 8 : 16);
+    if (const char* e = std::getenv("WAVEFD_BATCH_CX")) cx = std::max(1, std::min(L.nx, std::atoi(e)));
     step_plan(p, md.geom.ndim, md.half, false, cx, p.tile, 0);
     const int NT = block_threads(md, p);
     Injector inj;
