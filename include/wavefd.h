@@ -118,6 +118,19 @@ wf_status wf_model_set_m(wf_model* model, const float* m_dev, void* stream);
 /* Device bytes held by the model handle itself (fields, coefficients). */
 int64_t wf_model_bytes(const wf_model* model);
 
+/* Time loops of wf_forward / wf_adjoint on this model that were launched as a
+ * captured HIP graph. A call runs eagerly the first time its signature (dt,
+ * nt, point coordinates, every device pointer, save_every) is seen; when the
+ * same signature comes back within the next few calls, that call captures the
+ * whole loop on the model's own stream and launches it, and later calls with
+ * it replay the graph (up to four captured loops are kept per model, least
+ * recently used dropped first). Graph launches are ordered after earlier work
+ * on the caller's stream and before later work on it. The contents of the
+ * inputs (m, wavelets, data) may change between calls; only pointers and
+ * sizes are part of the signature. Capture is off while kernel timing is
+ * enabled or with WAVEFD_GRAPH=0. Returns -1 for a NULL model. */
+int64_t wf_model_graph_launches(const wf_model* model);
+
 /* Free the model and everything it holds. Synchronises its device work. */
 wf_status wf_model_destroy(wf_model* model);
 
@@ -169,8 +182,10 @@ int64_t wf_revolve_forward_steps(int64_t steps, int snaps);
 #define WF_KERNEL_INJECT  1   /* sparse injection                              */
 #define WF_KERNEL_SAMPLE  2   /* sparse interpolation                          */
 
-/* While enabled (process-wide), every launch of the three kernels above is
- * bracketed by a pair of HIP events recorded on the stream it runs on. */
+/* While enabled (process-wide), launches of the three kernels above are
+ * bracketed by a pair of HIP events recorded on the stream they run on:
+ * every launch for on == 1, every on-th launch of each kind for on > 1 (a
+ * lighter touch on the timed work), none for on == 0. */
 wf_status wf_profile_enable(int on);
 
 /* Synchronise on the recorded events and return, for kernel `kind`, the summed

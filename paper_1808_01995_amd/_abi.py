@@ -88,6 +88,7 @@ def _load():
         "wf_model_create": (I, [ctypes.POINTER(wf_geom), P, P, P]),
         "wf_model_set_m": (I, [P, P, P]),
         "wf_model_bytes": (I64, [P]),
+        "wf_model_graph_launches": (I64, [P]),
         "wf_model_destroy": (I, [P]),
         "wf_forward": (I, [P, D, I, I, P, P, I, P, P, P, I, P]),
         "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
@@ -112,7 +113,8 @@ lib = _load()
 
 # every symbol declared in include/wavefd.h
 EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
-           "wf_model_set_m", "wf_model_bytes", "wf_model_destroy", "wf_forward", "wf_adjoint",
+           "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches",
+           "wf_model_destroy", "wf_forward", "wf_adjoint",
            "wf_gradient", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
            "wf_engine_create", "wf_engine_submit",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
@@ -210,6 +212,10 @@ def wf_model_bytes(model) -> int:
     return int(lib.wf_model_bytes(model))
 
 
+def wf_model_graph_launches(model) -> int:
+    return int(lib.wf_model_graph_launches(model))
+
+
 def wf_model_destroy(model):
     _check(lib.wf_model_destroy(model))
 
@@ -248,8 +254,9 @@ WF_KERNEL_INJECT = 1
 WF_KERNEL_SAMPLE = 2
 
 
-def wf_profile_enable(on: bool):
-    _check(lib.wf_profile_enable(1 if on else 0))
+def wf_profile_enable(on):
+    """True/1: time every launch; n > 1: every n-th launch of each kernel; 0: off."""
+    _check(lib.wf_profile_enable(int(on)))
 
 
 def wf_profile_read(kind: int, reset: bool = False):

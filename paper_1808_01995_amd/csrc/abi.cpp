@@ -92,6 +92,11 @@ int64_t wf_model_bytes(const wf_model* model) {
     return static_cast<const Model*>(model)->bytes();
 }
 
+int64_t wf_model_graph_launches(const wf_model* model) {
+    if (!model) return -1;
+    return static_cast<const Model*>(model)->graph_launches;
+}
+
 wf_status wf_model_destroy(wf_model* model) {
     ABI_GUARD_BEGIN
     delete as_model(model);

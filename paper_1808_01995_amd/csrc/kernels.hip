@@ -20,6 +20,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 
 namespace wf {
@@ -595,7 +596,9 @@ int step_capacity(int ndim, int half, int tile, bool img) {
     // (halo rows get evicted before the neighbouring tile reads them): on the
     // 336^3 order-8 step, 4 blocks/CU ran 10% slower than 3.
     const int waves = ts.bz * ts.by / 64;
-    per = std::min(per, std::max(1, 12 / std::max(1, waves)));
+    int max_waves = 12;
+    if (const char* e = std::getenv("WAVEFD_WAVES_PER_CU")) max_waves = std::max(1, std::atoi(e));
+    per = std::min(per, std::max(1, max_waves / std::max(1, waves)));
     c = per * cus;
     return c;
 }

@@ -14,7 +14,8 @@ struct Rec {
 };
 
 std::mutex g_mu;
-bool g_on = false;
+int g_on = 0;                     // sampling stride, 0 = off
+int64_t g_seen[3] = {0, 0, 0};    // launches seen per kind while enabled
 std::vector<Rec> g_recs;          // recorded, not yet read
 std::vector<hipEvent_t> g_free;   // reusable events
 double g_ms[3] = {0, 0, 0};
@@ -57,9 +58,15 @@ wf_status drain(bool wait) {
 
 }  // namespace
 
+bool profiling_active() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_on > 0;
+}
+
 ProfScope::ProfScope(int k, hipStream_t st) : kind(k), s(st) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on) return;
+    if (g_on <= 0 || k < 0 || k > 2) return;
+    if (g_seen[k]++ % g_on != 0) return;
     if (g_recs.size() > 4096) drain(false);
     a = get_event();
     b = get_event();
@@ -88,8 +95,10 @@ using namespace wf;
 extern "C" {
 
 wf_status wf_profile_enable(int on) {
+    if (on < 0) return fail(WF_E_ARG, "negative profiling stride");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_on = on != 0;
+    g_on = on;
+    for (int k = 0; k < 3; ++k) g_seen[k] = 0;
     return WF_OK;
 }
 

@@ -80,8 +80,10 @@ struct Injector {
     const float* vals = nullptr;
     const float* inc = nullptr;
 
-    wf_status prepare(Model& md, const PointSet& set, const StepParams& p, const float* series,
-                      int nrows, DevBuf& buf, hipStream_t s) {
+    IncParams ip{};
+    // host side: tables and buffers (synchronous work, never captured)
+    wf_status plan(Model& md, const PointSet& set, const StepParams& p, const float* series,
+                   int nrows, DevBuf& buf, hipStream_t s) {
         ps = &set;
         vals = series;
         fz = nullptr;
@@ -96,7 +98,6 @@ struct Injector {
             WF_TRY(hip_check(hipStreamSynchronize(s), "sync"));   // buffer may be in use
             WF_TRY(buf.alloc(need));
         }
-        IncParams ip;
         ip.inc = buf.f();
         ip.kap = md.kap();
         ip.off = fz->off.as<int64_t>();
@@ -110,7 +111,17 @@ struct Injector {
         ip.nrows = nrows;
         ip.inv2dt = p.inv2dt;
         inc = buf.f();
+        return WF_OK;
+    }
+    // device side: the increments of every step
+    wf_status enqueue(hipStream_t s) const {
+        if (!fz) return WF_OK;
         return hip_check(launch_increments(ip, s), "increments");
+    }
+    wf_status prepare(Model& md, const PointSet& set, const StepParams& p, const float* series,
+                      int nrows, DevBuf& buf, hipStream_t s) {
+        WF_TRY(plan(md, set, p, series, nrows, buf, s));
+        return enqueue(s);
     }
     // configure the step that injects row `row`
     void configure(StepParams& p, int64_t row) const {
@@ -152,61 +163,167 @@ int block_threads(const Model& md, const StepParams& p) {
 
 }  // namespace
 
+// Time loops as HIP graphs: the host prepares everything first (plans,
+// tables, buffers); the enqueue phase (fills, increments, every step, the last
+// sample) is then either issued directly or captured once and replayed. A
+// signature (every pointer and size the loop bakes in) runs eagerly the first
+// time, is captured on its next call while still among the recent ones, and
+// replays from then on; a few captured loops are kept per model. Graphs run
+// on the model's own stream, ordered after and before the caller's stream
+// with events.
+namespace {
+
+int64_t bits_of(double x) {
+    int64_t b;
+    std::memcpy(&b, &x, sizeof b);
+    return b;
+}
+
+bool graphs_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("WAVEFD_GRAPH");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+wf_status launch_graph(Model& md, Model::GraphEntry& e, hipStream_t s) {
+    e.tick = ++md.graph_tick;
+    WF_TRY(hip_check(hipEventRecord(md.ev_in, s), "event"));
+    WF_TRY(hip_check(hipStreamWaitEvent(md.gstream, md.ev_in, 0), "wait"));
+    WF_TRY(hip_check(hipGraphLaunch(e.exec, md.gstream), "graph launch"));
+    ++md.graph_launches;
+    WF_TRY(hip_check(hipEventRecord(md.ev_out, md.gstream), "event"));
+    return hip_check(hipStreamWaitEvent(s, md.ev_out, 0), "wait");
+}
+
+// Replay a captured loop with this signature; else capture it if the
+// signature ran eagerly in one of the last calls; else run it eagerly.
+template <class F>
+wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enqueue) {
+    if (!graphs_enabled() || profiling_active()) return enqueue(s);
+    for (Model::GraphEntry& e : md.graphs)
+        if (e.key == key) return launch_graph(md, e, s);
+    auto it = std::find(md.seen.begin(), md.seen.end(), key);
+    if (it == md.seen.end()) {
+        if (md.seen.size() >= Model::kMaxSeen) md.seen.erase(md.seen.begin());
+        md.seen.push_back(key);
+        return enqueue(s);
+    }
+    md.seen.erase(it);
+    WF_TRY(md.ensure_graph_stream());
+    if (md.graphs.size() >= Model::kMaxGraphs) {   // evict the least recently used
+        auto lru = std::min_element(md.graphs.begin(), md.graphs.end(),
+                                    [](const Model::GraphEntry& a, const Model::GraphEntry& b) {
+                                        return a.tick < b.tick;
+                                    });
+        WF_TRY(hip_check(hipStreamSynchronize(md.gstream), "sync"));
+        (void)hipGraphExecDestroy(lru->exec);
+        (void)hipGraphDestroy(lru->graph);
+        md.graphs.erase(lru);
+    }
+    // capture on the model's stream, ordered after the caller's earlier work
+    WF_TRY(hip_check(hipEventRecord(md.ev_in, s), "event"));
+    WF_TRY(hip_check(hipStreamWaitEvent(md.gstream, md.ev_in, 0), "wait"));
+    WF_TRY(hip_check(hipStreamBeginCapture(md.gstream, hipStreamCaptureModeThreadLocal), "begin capture"));
+    const wf_status st = enqueue(md.gstream);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(md.gstream, &g);
+    if (st != WF_OK || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != WF_OK ? st : hip_check(ce, "end capture");
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_check(ie, "graph instantiate");
+    }
+    Model::GraphEntry e;
+    e.key = key;
+    e.graph = g;
+    e.exec = ex;
+    md.graphs.push_back(e);
+    return launch_graph(md, md.graphs.back(), s);
+}
+
+}  // namespace
+
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
                       hipStream_t s) {
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
-    float* A = md.u(0);   // u^n
-    float* B = md.u(1);   // u^{n-1}, overwritten by u^{n+1}
-    WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
-    WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
-    if (u_save) WF_TRY(hip_check(launch_fill(u_save, L.npoints, 0.0f, s), "fill"));
     StepParams p;
     md.fill_step(p, dt, false, rec.npts);
     const int NT = block_threads(md, p);
     Injector inj;
-    WF_TRY(inj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
-    if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, s), "fill"));
-    for (int n = 0; n + 1 < nt; ++n) {
-        // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
-        inj.configure(p, n);
-        set_sampling(p, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr, NT);
-        WF_TRY(step(p, md, A, B, B, false, nullptr, nullptr, s));
-        WF_TRY(inj.after(md, n, B, nullptr, nullptr, p, s));
-        if (u_save && (n + 1) % save_every == 0)
-            WF_TRY(hip_check(launch_unpitch(B, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
-                                            L.nx, L.ny, L.nz, L.sx, L.sy, s), "save"));
-        std::swap(A, B);
-    }
-    if (nt > 1) WF_TRY(sample(rec, A, rec_out + (int64_t)(nt - 1) * rec.npts, s));
-    return WF_OK;
+    WF_TRY(inj.plan(md, src, p, src_wav, nt, md.d_inc[0], s));
+    GraphKey key;
+    key.v = {0, (int64_t)nt, bits_of(dt), src.gen, rec.gen, (int64_t)(intptr_t)src_wav,
+             (int64_t)(intptr_t)rec_out, (int64_t)(intptr_t)u_save, save_every, p.cx, p.tile,
+             (int64_t)(intptr_t)inj.inc, (int64_t)(intptr_t)inj.fz, (int64_t)(intptr_t)md.u(0),
+             (int64_t)(intptr_t)md.u(1), (int64_t)(intptr_t)md.kap()};
+    auto enqueue = [&](hipStream_t q) -> wf_status {
+        float* A = md.u(0);   // u^n
+        float* B = md.u(1);   // u^{n-1}, overwritten by u^{n+1}
+        WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, q), "fill"));
+        WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, q), "fill"));
+        if (u_save) WF_TRY(hip_check(launch_fill(u_save, L.npoints, 0.0f, q), "fill"));
+        WF_TRY(inj.enqueue(q));
+        if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, q), "fill"));
+        StepParams ps = p;
+        for (int n = 0; n + 1 < nt; ++n) {
+            // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
+            inj.configure(ps, n);
+            set_sampling(ps, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr, NT);
+            WF_TRY(step(ps, md, A, B, B, false, nullptr, nullptr, q));
+            WF_TRY(inj.after(md, n, B, nullptr, nullptr, ps, q));
+            if (u_save && (n + 1) % save_every == 0)
+                WF_TRY(hip_check(launch_unpitch(B, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
+                                                L.nx, L.ny, L.nz, L.sx, L.sy, q), "save"));
+            std::swap(A, B);
+        }
+        if (nt > 1) WF_TRY(sample(rec, A, rec_out + (int64_t)(nt - 1) * rec.npts, q));
+        return WF_OK;
+    };
+    return run_maybe_graph(md, key, s, enqueue);
 }
 
 wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const float* rec_in,
                       const PointSet& src, float* src_out, hipStream_t s) {
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
-    float* A = md.u(0);   // v^{n+1}
-    float* B = md.u(1);   // v^{n+2}, overwritten by v^n
-    WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
-    WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
     StepParams p;
     md.fill_step(p, dt, false, src.npts);
     const int NT = block_threads(md, p);
     Injector inj;
-    WF_TRY(inj.prepare(md, rec, p, rec_in, nt, md.d_inc[0], s));
-    if (nt == 1 && src.npts > 0) WF_TRY(hip_check(launch_fill(src_out, src.npts, 0.0f, s), "fill"));
-    for (int n = nt - 2; n >= 0; --n) {
-        // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
-        inj.configure(p, n + 1);
-        set_sampling(p, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr, NT);
-        WF_TRY(step(p, md, A, B, B, false, nullptr, nullptr, s));
-        WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, p, s));
-        std::swap(A, B);
-    }
-    if (nt > 1) WF_TRY(sample(src, A, src_out, s));
-    return WF_OK;
+    WF_TRY(inj.plan(md, rec, p, rec_in, nt, md.d_inc[0], s));
+    GraphKey key;
+    key.v = {1, (int64_t)nt, bits_of(dt), rec.gen, src.gen, (int64_t)(intptr_t)rec_in,
+             (int64_t)(intptr_t)src_out, 0, 0, p.cx, p.tile, (int64_t)(intptr_t)inj.inc,
+             (int64_t)(intptr_t)inj.fz, (int64_t)(intptr_t)md.u(0), (int64_t)(intptr_t)md.u(1),
+             (int64_t)(intptr_t)md.kap()};
+    auto enqueue = [&](hipStream_t q) -> wf_status {
+        float* A = md.u(0);   // v^{n+1}
+        float* B = md.u(1);   // v^{n+2}, overwritten by v^n
+        WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, q), "fill"));
+        WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, q), "fill"));
+        WF_TRY(inj.enqueue(q));
+        if (nt == 1 && src.npts > 0) WF_TRY(hip_check(launch_fill(src_out, src.npts, 0.0f, q), "fill"));
+        StepParams ps = p;
+        for (int n = nt - 2; n >= 0; --n) {
+            // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
+            inj.configure(ps, n + 1);
+            set_sampling(ps, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr, NT);
+            WF_TRY(step(ps, md, A, B, B, false, nullptr, nullptr, q));
+            WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, ps, q));
+            std::swap(A, B);
+        }
+        if (nt > 1) WF_TRY(sample(src, A, src_out, q));
+        return WF_OK;
+    };
+    return run_maybe_graph(md, key, s, enqueue);
 }
 
 // ---------------------------------------------------------------------------

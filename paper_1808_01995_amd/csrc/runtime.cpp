@@ -3,6 +3,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -259,7 +260,10 @@ wf_status build_points(const wf_geom* g, const Layout& L, int npts, const double
     return WF_OK;
 }
 
+static std::atomic<int64_t> g_pointset_gen{1};
+
 wf_status PointSet::build(const wf_geom* g, const Layout& L, int npts_, const double* xyz) {
+    gen = g_pointset_gen.fetch_add(1);
     npts = npts_;
     K = 1 << g->ndim;
     nnodes = 0;
@@ -520,8 +524,30 @@ wf_status Model::points(int npts, const double* xyz, const PointSet** out) {
     return WF_OK;
 }
 
+wf_status Model::ensure_graph_stream() {
+    if (gstream) return WF_OK;
+    wf_status st = hip_check(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking), "stream");
+    if (st == WF_OK) st = hip_check(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming), "event");
+    if (st == WF_OK) st = hip_check(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming), "event");
+    return st;
+}
+
+void Model::drop_graphs() {
+    if (gstream) (void)hipStreamSynchronize(gstream);
+    for (GraphEntry& e : graphs) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
+    graphs.clear();
+    seen.clear();
+}
+
 Model::~Model() {
     (void)hipStreamSynchronize(last_stream);
+    drop_graphs();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (auto& c : pcache) delete c.ps;
 }
 

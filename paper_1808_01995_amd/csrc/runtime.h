@@ -84,6 +84,7 @@ struct FusedInj {
 // node-grouped table for deterministic injection.
 struct PointSet {
     int npts = 0, K = 0, nnodes = 0;
+    int64_t gen = 0;                            // unique id of this table (graph keys)
     DevBuf d_off, d_w;                          // [npts*K]
     DevBuf d_noff, d_neta, d_seg, d_ept, d_ew;  // injection by node
     std::vector<int64_t> h_noff;                // host copies of the node tables
@@ -100,6 +101,12 @@ struct PointSet {
 };
 
 }  // namespace wf
+
+// Signature of a captured time loop.
+struct GraphKey {
+    std::vector<int64_t> v;
+    bool operator==(const GraphKey& o) const { return v == o.v; }
+};
 
 struct PCache {
     uint64_t key = 0;
@@ -124,6 +131,23 @@ struct Model : public wf_model {
     std::vector<PCache> pcache;
     uint64_t tick = 0;
     hipStream_t last_stream = nullptr;   // the stream of the most recent work
+    // captured time loops (forward or adjoint), least recently used first out
+    struct GraphEntry {
+        GraphKey key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint64_t tick = 0;
+    };
+    static constexpr size_t kMaxGraphs = 4;   // captured loops kept per model
+    static constexpr size_t kMaxSeen = 8;     // signatures remembered for capture
+    std::vector<GraphEntry> graphs;
+    std::vector<GraphKey> seen;               // recent eager signatures, oldest first
+    uint64_t graph_tick = 0;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int64_t graph_launches = 0;
+    wf_status ensure_graph_stream();
+    void drop_graphs();
 
     ~Model() override;
     wf_status init(const wf_geom* g, const float* m_dev, hipStream_t s);
@@ -145,6 +169,7 @@ struct Model : public wf_model {
 namespace wf {
 
 // Kernel timing: while enabled, launches of `kind` are bracketed by events.
+bool profiling_active();
 struct ProfScope {
     int kind;
     hipStream_t s;

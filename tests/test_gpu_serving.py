@@ -101,8 +101,9 @@ def test_budget_admission_and_overlap():
         peak = max(peak, s["bytes_in_use"])
         assert s["bytes_in_use"] <= budget
     assert all(r.status == 0 for r in reqs)
-    # a short request arriving while a long one runs finishes first
-    long_r = _build([{"ndim": 2, "n": 400, "space_order": 8, "steps": 1500, "kind": "forward", "seed": 40}],
+    # a short request arriving while a long one runs finishes first (the long
+    # one is sized to run far longer than the 20 ms head start)
+    long_r = _build([{"ndim": 2, "n": 400, "space_order": 8, "steps": 12000, "kind": "forward", "seed": 40}],
                     nbl=20)[0]
     short_r = _build([{"ndim": 2, "n": 100, "space_order": 4, "steps": 60, "kind": "forward", "seed": 41}],
                      nbl=20)[0]
