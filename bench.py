@@ -104,6 +104,39 @@ def _timed(torch, fn, reps=1):
     return (time.perf_counter() - t) / reps, out
 
 
+def graph_c1(torch, shots=20):
+    """141^2 computational (101^2 + 20-node layer), order 4, 500 updates:
+    the time loop launched kernel by kernel against the same loop replayed
+    from its captured HIP graph (launch cost dominates at this size)."""
+    from paper_1808_01995_amd import Propagator, _abi
+    from synthetic import config, ricker
+    c = config("c1_2d")
+    v = c.velocity()
+    prop = Propagator(v, spacing=c.spacing, nbl=c.nbl, space_order=c.space_order)
+    dt = c.dt_factor * prop.critical_dt()
+    q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    rec = torch.empty((c.nt, c.rec.shape[0]), device="cuda")
+
+    def shot():
+        prop.forward(dt, c.nt, c.src, q, c.rec, rec_out=rec)
+
+    res = {"workload": "C1: 141^2 computational, order 4, %d updates, 101 receivers" % c.steps}
+    for mode in ("eager", "graph"):
+        _abi.wf_graph_enable(mode == "graph")
+        shot()
+        shot()     # graph mode: captured here
+        g0 = _abi.wf_model_graph_launches(prop.handle)
+        el, _ = _timed(torch, shot, reps=shots)
+        res[mode] = {"ms_per_shot": round(el * 1e3, 3), "us_per_update": round(el / c.steps * 1e6, 2),
+                     "gpts": round(prop.npoints * c.steps / el / 1e9, 3),
+                     "graph_launches": _abi.wf_model_graph_launches(prop.handle) - g0}
+    _abi.wf_graph_enable(False)
+    res["graph_speedup"] = round(res["eager"]["ms_per_shot"] / res["graph"]["ms_per_shot"], 2)
+    prop.close()
+    log("c1: %s" % res)
+    return res
+
+
 def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
     """512^3 physical (592^3 computational), two-layer 1.5/2.5 km/s, one
     shot per order: GPts/s and the step kernel's algorithmic bandwidth."""
@@ -233,7 +266,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
     ap.add_argument("--rows", default="",
-                    help="comma list of further rows to measure: c3,c4,serve (or all)")
+                    help="comma list of further rows to measure: c1,c3,c4,serve (or all)")
     ap.add_argument("--updates", type=int, default=None,
                     help="shorter shots (profiling runs only; the benchmark uses 1000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -285,6 +318,7 @@ def main():
 
     # the same shots launched as a captured HIP graph (kernel timing off, so
     # the loop is captured on the first call with an unchanged signature)
+    _abi.wf_graph_enable(True)
     g0 = _abi.wf_model_graph_launches(prop.handle)
     shot()
     torch.cuda.synchronize()
@@ -294,6 +328,7 @@ def main():
     torch.cuda.synchronize()
     el_graph = time.perf_counter() - t0
     g_launches = _abi.wf_model_graph_launches(prop.handle) - g0
+    _abi.wf_graph_enable(False)
 
     ms_per_shot = el / args.steps * 1e3
     updates = npts * c.steps
@@ -347,7 +382,9 @@ def main():
     prop.close()
     rows = set(x for x in args.rows.split(",") if x)
     if "all" in rows:
-        rows = {"c3", "c4", "serve"}
+        rows = {"c1", "c3", "c4", "serve"}
+    if "c1" in rows:
+        out["c1_graph"] = graph_c1(torch)
     if "c3" in rows:
         out["c3_sweep"] = sweep_c3(torch)
     if "c4" in rows:

@@ -119,17 +119,24 @@ wf_status wf_model_set_m(wf_model* model, const float* m_dev, void* stream);
 int64_t wf_model_bytes(const wf_model* model);
 
 /* Time loops of wf_forward / wf_adjoint on this model that were launched as a
- * captured HIP graph. A call runs eagerly the first time its signature (dt,
- * nt, point coordinates, every device pointer, save_every) is seen; when the
- * same signature comes back within the next few calls, that call captures the
- * whole loop on the model's own stream and launches it, and later calls with
- * it replay the graph (up to four captured loops are kept per model, least
- * recently used dropped first). Graph launches are ordered after earlier work
- * on the caller's stream and before later work on it. The contents of the
- * inputs (m, wavelets, data) may change between calls; only pointers and
- * sizes are part of the signature. Capture is off while kernel timing is
- * enabled or with WAVEFD_GRAPH=0. Returns -1 for a NULL model. */
+ * captured HIP graph. While capture is enabled (wf_graph_enable), a call runs
+ * eagerly the first time its signature (dt, nt, point coordinates, every
+ * device pointer, save_every) is seen; when the same signature comes back
+ * within the next few calls, that call captures the whole loop on the model's
+ * own stream and launches it, and later calls with it replay the graph (up to
+ * four captured loops are kept per model, least recently used dropped first).
+ * Graph launches are ordered after earlier work on the caller's stream and
+ * before later work on it. The contents of the inputs (m, wavelets, data) may
+ * change between calls; only pointers and sizes are part of the signature.
+ * Kernel timing (wf_profile_enable) suspends capture. Returns -1 for a NULL
+ * model. */
 int64_t wf_model_graph_launches(const wf_model* model);
+
+/* Process-wide switch for that capture: 1 on, 0 off. Off by default (a
+ * replayed kernel node was measured slower than a stream launch on ROCm 7.x),
+ * on at start-up when the environment sets WAVEFD_GRAPH=1. Captured loops are
+ * kept while it is off and used again once it is switched back on. */
+wf_status wf_graph_enable(int on);
 
 /* Free the model and everything it holds. Synchronises its device work. */
 wf_status wf_model_destroy(wf_model* model);

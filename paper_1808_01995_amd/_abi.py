@@ -89,6 +89,7 @@ def _load():
         "wf_model_set_m": (I, [P, P, P]),
         "wf_model_bytes": (I64, [P]),
         "wf_model_graph_launches": (I64, [P]),
+        "wf_graph_enable": (I, [I]),
         "wf_model_destroy": (I, [P]),
         "wf_forward": (I, [P, D, I, I, P, P, I, P, P, P, I, P]),
         "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
@@ -113,7 +114,7 @@ lib = _load()
 
 # every symbol declared in include/wavefd.h
 EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
-           "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches",
+           "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches", "wf_graph_enable",
            "wf_model_destroy", "wf_forward", "wf_adjoint",
            "wf_gradient", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
            "wf_engine_create", "wf_engine_submit",
@@ -214,6 +215,10 @@ def wf_model_bytes(model) -> int:
 
 def wf_model_graph_launches(model) -> int:
     return int(lib.wf_model_graph_launches(model))
+
+
+def wf_graph_enable(on: bool):
+    _check(lib.wf_graph_enable(1 if on else 0))
 
 
 def wf_model_destroy(model):

@@ -92,6 +92,11 @@ int64_t wf_model_bytes(const wf_model* model) {
     return static_cast<const Model*>(model)->bytes();
 }
 
+wf_status wf_graph_enable(int on) {
+    set_graphs_enabled(on != 0);
+    return WF_OK;
+}
+
 int64_t wf_model_graph_launches(const wf_model* model) {
     if (!model) return -1;
     return static_cast<const Model*>(model)->graph_launches;

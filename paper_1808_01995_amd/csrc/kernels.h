@@ -44,12 +44,13 @@ struct StepParams {
     float idt2;
     int tile;            // host side: which compiled tile shape step_plan chose
 
-    // Fused sampling of `cur`: the first smp_blocks blocks of the launch
-    // write smp_out[i] = sum_k smp_w[i*K+k] cur[smp_off[i*K+k]].
+    // Fused sampling of `cur`: block r (tile index) writes, for i in
+    // [r smp_per, (r + 1) smp_per), smp_out[i] = sum_k smp_w[i*K+k] cur[smp_off[i*K+k]]
+    // with K = 2^D corners per point.
     const int64_t* smp_off;
     const float* smp_w;
     float* smp_out;      // NULL: no sampling
-    int smp_n, smp_K, smp_blocks;
+    int smp_n, smp_per;
 
     // Fused injection into `out`: nodes grouped by block (inj_blk, nblocks+1
     // offsets), inside a block by (thread, x); thread t of block b owns the
@@ -90,10 +91,8 @@ struct TileShape {
 
 TileShape step_tile(int ndim, int tile);
 // Choose the tile shape and the x-chunking (ntz/nty/nchunks/nblocks/cx); a
-// positive cx_request forces the chunk length, tile_request >= 0 the shape;
-// reserve_blocks resident slots are left to the sampling blocks.
-void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request,
-               int reserve_blocks = 0);
+// positive cx_request forces the chunk length, tile_request >= 0 the shape.
+void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request);
 // Threads per block of the step kernel for a dimension and tile shape.
 int step_threads(int ndim, int tile);
 hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s);

@@ -116,19 +116,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
     __shared__ int inj_cl[kInjCap];
     __shared__ float inj_vl[kInjCap];
 
-    if (bidx < p.smp_blocks) {
-        // sampling role (the first blocks dispatched, spread over every XCD):
-        // interpolate the current field at the receivers
-        const int i = bidx * NT + (int)threadIdx.x;
-        if (i < p.smp_n) {
-            float acc = 0.0f;
-            for (int k = 0; k < p.smp_K; ++k)
-                acc = fmaf(p.smp_w[(int64_t)i * p.smp_K + k], p.cur[p.smp_off[(int64_t)i * p.smp_K + k]], acc);
-            p.smp_out[i] = acc;
-        }
-        return;
-    }
-    const int r = xcd_remap(bidx - p.smp_blocks, p.nblocks);
+    const int r = xcd_remap(bidx, p.nblocks);
     if (r >= p.nblocks) return;
     int t = r;
     const int itz = t % p.ntz;
@@ -232,6 +220,27 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
         for (int j = 0; j < JZ; ++j) hz_n[j] = ld4(p.cur + b + hz_c[j]);
     };
     load_next(xb);
+
+    // this block's share of the receivers: interpolate cur (which the step
+    // only reads); issued after the prologue loads so that the gather's
+    // latency overlaps theirs. The corner order matches k_sample.
+    if (p.smp_out) {
+        constexpr int KS = D3 ? 8 : 4;   // corners of a cell
+        const int s0 = r * p.smp_per, s1 = min(s0 + p.smp_per, p.smp_n);
+        for (int i = s0 + tid; i < s1; i += NT) {
+            int64_t so[KS];
+            float sw[KS];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                so[k] = p.smp_off[(int64_t)i * KS + k];
+                sw[k] = p.smp_w[(int64_t)i * KS + k];
+            }
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) acc = fmaf(sw[k], p.cur[so[k]], acc);
+            p.smp_out[i] = acc;
+        }
+    }
 
     for (int xg = xb; xg < xe; xg += NQ) {
 #pragma unroll
@@ -615,8 +624,7 @@ TileShape step_tile(int ndim, int tile) {
     return kTile2;
 }
 
-void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request,
-               int reserve_blocks) {
+void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request) {
     int tile = 0;
     if (ndim == 3) {
         if (tile_request == 0 || tile_request == 1) {
@@ -636,10 +644,7 @@ void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, 
         // Chunks along x trade parallelism against the 2M + PF planes every
         // chunk re-reads to fill its register ring. Cost model per resident
         // round of blocks: (planes + warm-up) / occupancy, times the rounds.
-        // the sampling blocks of the launch are dispatched first and finish
-        // within microseconds, so they only take slots when they are many
-        const int full = step_capacity(ndim, half, tile, imaging);
-        const int cap = reserve_blocks > full / 4 ? std::max(full - reserve_blocks, full / 2) : full;
+        const int cap = step_capacity(ndim, half, tile, imaging);
         const int warm = 2 * half + 1;
         double best = 1e300;
         int best_n = 1;
@@ -667,7 +672,7 @@ hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hi
     const void* fn = step_fn(ndim, half, p.tile, imaging);
     if (!fn) return hipErrorInvalidValue;
     const TileShape ts = step_tile(ndim, p.tile);
-    const int grid = p.smp_blocks + ((p.nblocks + 7) / 8) * 8;
+    const int grid = ((p.nblocks + 7) / 8) * 8;
     void* args[] = {const_cast<StepParams*>(&p)};
     return hipLaunchKernel(fn, dim3(grid), dim3(ts.bz * ts.by), args, 0, s);
 }

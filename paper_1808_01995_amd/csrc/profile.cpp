@@ -27,8 +27,10 @@ hipEvent_t get_event() {
         g_free.pop_back();
         return e;
     }
+    // timing-only events: no system-scope fence (its cache writeback and
+    // invalidation would otherwise slow the bracketed kernel)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

@@ -14,6 +14,7 @@
 // term j = n+1 is accumulated by the adjoint step n, inside the stencil kernel
 // for the pre-injection v^n and by the injection kernel for the injected part.
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -141,10 +142,11 @@ struct Injector {
     }
 };
 
-void set_sampling(StepParams& p, const PointSet* ps, float* out, int NT) {
+// Receivers spread evenly over the blocks of the (already planned) launch.
+void set_sampling(StepParams& p, const PointSet* ps, float* out) {
     if (!ps || ps->npts == 0 || !out) {
         p.smp_out = nullptr;
-        p.smp_blocks = 0;
+        p.smp_per = 0;
         p.smp_n = 0;
         return;
     }
@@ -152,14 +154,9 @@ void set_sampling(StepParams& p, const PointSet* ps, float* out, int NT) {
     p.smp_w = ps->d_w.f();
     p.smp_out = out;
     p.smp_n = ps->npts;
-    p.smp_K = ps->K;
-    p.smp_blocks = (ps->npts + NT - 1) / NT;
+    p.smp_per = (int)(((int64_t)ps->npts + p.nblocks - 1) / p.nblocks);
 }
 
-int block_threads(const Model& md, const StepParams& p) {
-    const TileShape ts = step_tile(md.geom.ndim, p.tile);
-    return ts.bz * ts.by;
-}
 
 }  // namespace
 
@@ -179,13 +176,18 @@ int64_t bits_of(double x) {
     return b;
 }
 
-bool graphs_enabled() {
-    static const bool on = [] {
+// Off unless asked for: on ROCm 7.x a replayed kernel node costs 0.5-1 us
+// more than the same launch issued to a stream (measured from 2e4 to 4e7
+// nodes), so graphs pay only where a caller needs the loop as one unit.
+std::atomic<int>& graph_switch() {
+    static std::atomic<int> on{[] {
         const char* e = std::getenv("WAVEFD_GRAPH");
-        return !(e && e[0] == '0');
-    }();
+        return (e && e[0] == '1') ? 1 : 0;
+    }()};
     return on;
 }
+
+bool graphs_enabled() { return graph_switch().load(std::memory_order_relaxed) != 0; }
 
 wf_status launch_graph(Model& md, Model::GraphEntry& e, hipStream_t s) {
     e.tick = ++md.graph_tick;
@@ -249,14 +251,15 @@ wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enq
 
 }  // namespace
 
+void set_graphs_enabled(bool on) { graph_switch().store(on ? 1 : 0); }
+
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
                       hipStream_t s) {
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
     StepParams p;
-    md.fill_step(p, dt, false, rec.npts);
-    const int NT = block_threads(md, p);
+    md.fill_step(p, dt, false);
     Injector inj;
     WF_TRY(inj.plan(md, src, p, src_wav, nt, md.d_inc[0], s));
     GraphKey key;
@@ -276,7 +279,7 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
         for (int n = 0; n + 1 < nt; ++n) {
             // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
             inj.configure(ps, n);
-            set_sampling(ps, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr, NT);
+            set_sampling(ps, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr);
             WF_TRY(step(ps, md, A, B, B, false, nullptr, nullptr, q));
             WF_TRY(inj.after(md, n, B, nullptr, nullptr, ps, q));
             if (u_save && (n + 1) % save_every == 0)
@@ -295,8 +298,7 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
     StepParams p;
-    md.fill_step(p, dt, false, src.npts);
-    const int NT = block_threads(md, p);
+    md.fill_step(p, dt, false);
     Injector inj;
     WF_TRY(inj.plan(md, rec, p, rec_in, nt, md.d_inc[0], s));
     GraphKey key;
@@ -315,7 +317,7 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
         for (int n = nt - 2; n >= 0; --n) {
             // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
             inj.configure(ps, n + 1);
-            set_sampling(ps, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr, NT);
+            set_sampling(ps, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr);
             WF_TRY(step(ps, md, A, B, B, false, nullptr, nullptr, q));
             WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, ps, q));
             std::swap(A, B);
@@ -508,16 +510,14 @@ wf_status batch_forward_begin(Model& md, double dt, int nt, const PointSet& src,
     // stream of orders 4/8/12: 8 planes best in 2D, 16 in 3D)
     int cx = std::min(L.nx, md.geom.ndim == 2 ? 8 : 16);
     if (const char* e = std::getenv("WAVEFD_BATCH_CX")) cx = std::max(1, std::min(L.nx, std::atoi(e)));
-    step_plan(p, md.geom.ndim, md.half, false, cx, p.tile, 0);
-    const int NT = block_threads(md, p);
+    step_plan(p, md.geom.ndim, md.half, false, cx, p.tile);
     Injector inj;
     WF_TRY(inj.prepare(md, src, p, wav, nt, md.d_inc[0], s));
     if (src.nnodes > 0 && !inj.fz) return fail(WF_E_STATE, "sources cannot be injected by the batched kernel");
     inj.configure(p, 0);
     b.inj_stride = inj.fz ? inj.fz->nnodes : 0;
-    set_sampling(p, &rec, rec.npts ? rec_out : nullptr, NT);
-    p.smp_blocks = (p.smp_blocks + 7) / 8 * 8;   // keep the stencil blocks XCD-aligned
-    b.nblk = p.smp_blocks + (p.nblocks + 7) / 8 * 8;
+    set_sampling(p, &rec, rec.npts ? rec_out : nullptr);
+    b.nblk = (p.nblocks + 7) / 8 * 8;
     if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, s), "fill"));
     return WF_OK;
 }

@@ -551,7 +551,7 @@ Model::~Model() {
     for (auto& c : pcache) delete c.ps;
 }
 
-void Model::fill_step(StepParams& p, double dt, bool imaging, int sample_points) const {
+void Model::fill_step(StepParams& p, double dt, bool imaging) const {
     std::memset(&p, 0, sizeof p);
     p.kap = kap();
     p.etax = d_etax.f();
@@ -578,12 +578,5 @@ void Model::fill_step(StepParams& p, double dt, bool imaging, int sample_points)
     int cx = 0, tile = -1;
     if (const char* s = std::getenv("WAVEFD_CX")) cx = std::atoi(s);
     if (const char* s = std::getenv("WAVEFD_TILE")) tile = std::atoi(s);
-    // the sampling blocks of the same launch reserve resident slots
-    int reserve = 0;
-    if (sample_points > 0) {
-        const int tz = tile >= 0 ? tile : (geom.ndim == 3 && L.nz < 96 ? 1 : 0);
-        const int nt = step_threads(geom.ndim, tz);
-        reserve = (sample_points + nt - 1) / nt;
-    }
-    step_plan(p, geom.ndim, half, imaging, cx, tile, reserve);
+    step_plan(p, geom.ndim, half, imaging, cx, tile);
 }

@@ -157,7 +157,7 @@ struct Model : public wf_model {
     double vmax() const;
     wf_status points(int npts, const double* xyz, const wf::PointSet** out);
     // plan a step launch; sample_points > 0 leaves room for that many fused samples
-    void fill_step(wf::StepParams& p, double dt, bool imaging = false, int sample_points = 0) const;
+    void fill_step(wf::StepParams& p, double dt, bool imaging = false) const;
     float* u(int i) const { return L.field(d_u[i].ptr); }
     float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
@@ -179,6 +179,8 @@ struct ProfScope {
 };
 
 // Time loops (propagate.cpp).
+// Process-wide switch for capturing time loops as HIP graphs.
+void set_graphs_enabled(bool on);
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
                       hipStream_t s);

@@ -4,7 +4,8 @@ after). Every replay must equal the eager run bitwise, with other eager work
 on the same model and stream between replays, and must follow in-place
 changes of the inputs (wavelet, m) exactly as a fresh eager run does.
 All buffers are explicit so that the signatures, and so the launch counts,
-do not depend on the caching allocator.
+do not depend on the caching allocator. Capture is switched on for these
+tests (it is off by default).
 """
 import numpy as np
 import pytest
@@ -19,6 +20,13 @@ torch = pytest.importorskip("torch")
 def _abi():
     from paper_1808_01995_amd import _abi
     return _abi
+
+
+@pytest.fixture(autouse=True)
+def _graphs_on():
+    _abi().wf_graph_enable(True)
+    yield
+    _abi().wf_graph_enable(False)
 
 
 def _setup(shape, k, steps, seed):
@@ -153,3 +161,17 @@ def test_graph_cache_eviction():
     # were consumed by their capture, so they run eagerly again and the LRU
     # loops 2..5 replay
     assert _launches(prop) == n0 + 6 + 4
+
+
+def test_capture_off_runs_eagerly():
+    """With capture switched off, repeated calls never launch a graph."""
+    P, prop, q, rec = _setup((50, 40), 4, 30, seed=43)
+    _abi().wf_graph_enable(False)
+    n0 = _launches(prop)
+    outs = []
+    for _ in range(3):
+        _abi().wf_forward(prop.handle, P.dt, P.nt, P.src_xyz, q, P.rec_xyz, rec)
+        torch.cuda.synchronize()
+        outs.append(rec.clone())
+    assert _launches(prop) == n0
+    assert torch.equal(outs[1], outs[0]) and torch.equal(outs[2], outs[0])
