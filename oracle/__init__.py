@@ -53,7 +53,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 __all__ = [
     "build", "fd_weights", "fd_weights_float", "abs_weight_sum", "critical_dt",
     "pad_edge", "damping_eta", "sparse_points", "Grid", "laplacian", "step",
-    "forward", "adjoint", "gradient", "energy", "misfit",
+    "forward", "adjoint", "gradient", "energy", "misfit", "fwi_objective", "fwi_update",
 ]
 
 
@@ -401,6 +401,41 @@ def gradient(grid: Grid, m: np.ndarray, eta: np.ndarray, dt: float, nt: int,
     if rc != 0:
         raise MemoryError("oracle_gradient")
     return (g1, g2) if both else g1
+
+
+def fwi_objective(grid: Grid, m: np.ndarray, eta: np.ndarray, dt: float, nt: int,
+                  shots, d_obs):
+    """Multi-shot FWI objective and gradient (eq. AS summed over the source
+    experiments; Section "FWI using Devito operators": a loop over the shots
+    whose gradients are added). For shot s = (src, q, rec):
+        d_s = P_r A(m)^{-1} P_s^T q_s,  r_s = d_s - d_obs[s],
+        Phi = sum_s 1/2 ||r_s||^2,     g = sum_s J_s^T r_s  (eq. Grad per shot).
+    Returns (Phi, g, [d_s])."""
+    phi = 0.0
+    g = None
+    preds = []
+    for (src, q, rec), dob in zip(shots, d_obs):
+        d = forward(grid, m, eta, dt, nt, src, q, rec)
+        r = d - dob
+        phi = phi + misfit(d, dob)
+        gs = gradient(grid, m, eta, dt, nt, src, q, rec, r)
+        g = gs if g is None else g + gs
+        preds.append(d)
+    return phi, g, preds
+
+
+def fwi_update(m: np.ndarray, g: np.ndarray, alpha: float,
+               m_lo: Optional[float] = None, m_hi: Optional[float] = None) -> np.ndarray:
+    """One fixed-step gradient update of the squared slowness, m - alpha g
+    (the steepest-descent step of Section "FWI using Devito operators"),
+    projected onto the box [m_lo, m_hi] (velocity bounds 1/vmax^2 <= m <=
+    1/vmin^2, the bound constraints of the inversion example)."""
+    out = np.asarray(m, dtype=np.float64) - alpha * np.asarray(g, dtype=np.float64)
+    if m_lo is not None:
+        out = np.maximum(out, m_lo)
+    if m_hi is not None:
+        out = np.minimum(out, m_hi)
+    return out
 
 
 def energy(grid: Grid, m: np.ndarray, dt: float, u_n: np.ndarray, u_np1: np.ndarray) -> float:
