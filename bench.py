@@ -215,6 +215,45 @@ def gradient_c4(torch, steps=2000, snaps=(-1, 50, 20)):
     return out
 
 
+def fwi_multishot(torch, steps=2000, iters=3):
+    """Multi-shot FWI on the 280^3 order-8 gradient workload: 4 sources at
+    20 m depth on a 2 x 2 pattern, the 100 x 100 receiver grid for each;
+    per iteration the summed gradient (two wave solves per shot, store-all or
+    revolve as memory allows) and one fixed-step update. The observed data
+    are modelled on the true model with the same forward (a timing row)."""
+    from paper_1808_01995_amd import Propagator
+    from synthetic import config, ricker
+    c = config("c4_gradient", steps=steps)
+    v_true = c.velocity()
+    pt = Propagator(v_true, spacing=c.spacing, nbl=c.nbl, space_order=8, c_ref=2.5)
+    dt = 0.5 * pt.critical_dt(2.5)
+    q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    ext = (c.shape[0] - 1) * c.spacing[0]
+    srcs = [np.array([[fx * ext, fy * ext, 20.0]]) for fx in (0.25, 0.75) for fy in (0.25, 0.75)]
+    shots = [(sx, q, c.rec, pt.forward(dt, c.nt, sx, q, c.rec)) for sx in srcs]
+    pt.close()
+    p0 = Propagator(np.full(c.shape, 2.0), spacing=c.spacing, nbl=c.nbl, space_order=8, c_ref=2.5)
+    its = []
+    for it in range(iters):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        phi, g = p0.fwi_gradient(dt, c.nt, shots)
+        alpha = 0.001 * float(p0.m.abs().max()) / float(g.abs().max())
+        p0.update(g, alpha, vmin=1.5, vmax=2.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        its.append({"seconds": round(el, 3), "misfit": phi,
+                    "shots_per_s": round(len(shots) / el, 2),
+                    "gpts_effective": round(2 * len(shots) * p0.npoints * c.steps / el / 1e9, 1)})
+        log("fwi iteration %d: %s" % (it, its[-1]))
+    p0.close()
+    return {"workload": "280^3 computational, order 8, %d updates, 4 shots x 100x100 receivers, "
+                        "fixed-step update (0.1 %% of max m per step) with 1.5-2.5 km/s bounds" % steps,
+            "iterations": its,
+            "note": "gpts_effective counts two wave solves per shot; the first iteration also "
+                    "allocates the model's gradient workspace (store-all: 2001 fields, 176 GB)"}
+
+
 def serving_c5(torch, n_requests=48, scale_down=2, max_steps=1000, seed=5):
     """Reduced serving stream (grid sizes divided by `scale_down`, steps capped):
     one-shot-per-launch baseline mu_0, saturated throughput, Poisson arrivals."""
@@ -266,7 +305,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
     ap.add_argument("--rows", default="",
-                    help="comma list of further rows to measure: c1,c3,c4,serve (or all)")
+                    help="comma list of further rows to measure: c1,c3,c4,fwi,serve (or all)")
     ap.add_argument("--updates", type=int, default=None,
                     help="shorter shots (profiling runs only; the benchmark uses 1000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -382,13 +421,15 @@ def main():
     prop.close()
     rows = set(x for x in args.rows.split(",") if x)
     if "all" in rows:
-        rows = {"c1", "c3", "c4", "serve"}
+        rows = {"c1", "c3", "c4", "fwi", "serve"}
     if "c1" in rows:
         out["c1_graph"] = graph_c1(torch)
     if "c3" in rows:
         out["c3_sweep"] = sweep_c3(torch)
     if "c4" in rows:
         out["c4_gradient"] = gradient_c4(torch)
+    if "fwi" in rows:
+        out["fwi_multishot"] = fwi_multishot(torch)
     if "serve" in rows:
         out["c5_serving"] = serving_c5(torch)
     if not args.no_cpu:

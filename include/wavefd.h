@@ -115,8 +115,15 @@ wf_status wf_model_create(const wf_geom* geom, const float* m_dev, void* stream,
 /* Replace the model's squared slowness (same layout as in create). */
 wf_status wf_model_set_m(wf_model* model, const float* m_dev, void* stream);
 
-/* Device bytes held by the model handle itself (fields, coefficients). */
+/* Device bytes held by the model handle itself (fields, coefficients, sparse
+ * tables, and the gradient workspace: the checkpoint pool of the last
+ * gradient call is kept for the next one, because allocating tens of GB of
+ * device memory again costs seconds). */
 int64_t wf_model_bytes(const wf_model* model);
+
+/* Free the model's cached gradient workspace; the next gradient call
+ * allocates it again. Synchronises the model's device work. */
+wf_status wf_model_trim(wf_model* model);
 
 /* Time loops of wf_forward / wf_adjoint on this model that were launched as a
  * captured HIP graph. While capture is enabled (wf_graph_enable), a call runs
@@ -174,6 +181,47 @@ wf_status wf_gradient(wf_model* model, double dt, int nt,
                       int nrec, const double* rec_xyz, const float* residual,
                       float* grad_out, int n_checkpoints, int64_t hbm_budget_bytes,
                       void* stream);
+
+/* One source experiment of a multi-shot inversion.
+ *   src_xyz host FP64 [nsrc][ndim];  src_wav device FP32 [nt][nsrc]
+ *   rec_xyz host FP64 [nrec][ndim];  d_obs   device FP32 [nt][nrec]
+ *   d_pred  device FP32 [nt][nrec] or NULL: receives P_r u at the current m */
+typedef struct {
+    int nsrc;
+    const double* src_xyz;
+    const float* src_wav;
+    int nrec;
+    const double* rec_xyz;
+    const float* d_obs;
+    float* d_pred;
+} wf_shot;
+
+/* Multi-shot FWI objective and gradient (Section "FWI using Devito
+ * operators": a loop over the source experiments whose gradients are summed;
+ * eq. AS per shot). For every shot s, d_s = P_r A(m)^{-1} P_s^T q_s and
+ * r_s = d_s - d_obs,s;
+ *   misfit_out (host, may be NULL) = 1/2 sum_s ||r_s||^2 (FP64 partial sums
+ *              added in a fixed order),
+ *   grad_out   (device FP32 Nc^D, dense, overwritten) = sum_s J_s^T r_s.
+ * Each shot costs two wave solves: the residual is formed from the record of
+ * the gradient's own first forward sweep (plus the recomputation of revolve).
+ * n_checkpoints and hbm_budget_bytes apply to each shot as in wf_gradient
+ * (the accumulator and the record scratch count against the budget).
+ * nshots >= 1; synchronises `stream` (the misfit is a host value). */
+wf_status wf_fwi_gradient(wf_model* model, double dt, int nt, int nshots, const wf_shot* shots,
+                          float* grad_out, double* misfit_out, int n_checkpoints,
+                          int64_t hbm_budget_bytes, void* stream);
+
+/* Fixed-step gradient update of the model's squared slowness (the step of
+ * Section "FWI using Devito operators"), projected on bounds:
+ *   m <- min(max(m - alpha grad, m_lo), m_hi)  elementwise (one FP32 fma),
+ * grad device FP32 Nc^D (dense; every value finite, else WF_E_NONFINITE and m
+ * is unchanged), 0 < m_lo <= m_hi (1/vmax^2 and 1/vmin^2; m_hi may be +inf).
+ * m_out (device FP32 Nc^D or NULL) receives the new m. The coefficients are
+ * recomputed at the next call, whose dt is checked against the new vmax.
+ * Synchronises `stream`. */
+wf_status wf_model_update(wf_model* model, const float* grad, double alpha, double m_lo,
+                          double m_hi, float* m_out, void* stream);
 
 /* Number of forward time steps the revolve schedule of wf_gradient performs
  * for `steps` updates and `snaps` stored states (steps >= 1, snaps >= 1):

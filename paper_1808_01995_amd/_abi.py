@@ -71,6 +71,16 @@ class wf_request(ctypes.Structure):
                 ("misfit_out", ctypes.c_void_p)]
 
 
+class wf_shot(ctypes.Structure):
+    _fields_ = [("nsrc", ctypes.c_int),
+                ("src_xyz", ctypes.c_void_p),
+                ("src_wav", ctypes.c_void_p),
+                ("nrec", ctypes.c_int),
+                ("rec_xyz", ctypes.c_void_p),
+                ("d_obs", ctypes.c_void_p),
+                ("d_pred", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libwavefd.so is not built (run __graft_entry__.build() or "
@@ -89,11 +99,14 @@ def _load():
         "wf_model_set_m": (I, [P, P, P]),
         "wf_model_bytes": (I64, [P]),
         "wf_model_graph_launches": (I64, [P]),
+        "wf_model_trim": (I, [P]),
         "wf_graph_enable": (I, [I]),
         "wf_model_destroy": (I, [P]),
         "wf_forward": (I, [P, D, I, I, P, P, I, P, P, P, I, P]),
         "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
         "wf_gradient": (I, [P, D, I, I, P, P, I, P, P, P, I, I64, P]),
+        "wf_fwi_gradient": (I, [P, D, I, I, ctypes.POINTER(wf_shot), P, P, I, I64, P]),
+        "wf_model_update": (I, [P, P, D, D, D, P, P]),
         "wf_revolve_forward_steps": (I64, [I64, I]),
         "wf_profile_enable": (I, [I]),
         "wf_profile_read": (I, [I, P, P, I]),
@@ -115,8 +128,9 @@ lib = _load()
 # every symbol declared in include/wavefd.h
 EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
            "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches", "wf_graph_enable",
+           "wf_model_trim",
            "wf_model_destroy", "wf_forward", "wf_adjoint",
-           "wf_gradient", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
+           "wf_gradient", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
            "wf_engine_create", "wf_engine_submit",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
 
@@ -217,6 +231,10 @@ def wf_model_graph_launches(model) -> int:
     return int(lib.wf_model_graph_launches(model))
 
 
+def wf_model_trim(model):
+    _check(lib.wf_model_trim(model))
+
+
 def wf_graph_enable(on: bool):
     _check(lib.wf_graph_enable(1 if on else 0))
 
@@ -248,6 +266,32 @@ def wf_gradient(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, residual, 
     _check(lib.wf_gradient(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None,
                            nr, rp, _ptr(residual) if nr else None, _ptr(grad_out),
                            int(n_checkpoints), int(hbm_budget_bytes), _stream(stream)))
+
+
+def wf_fwi_gradient(model, dt: float, nt: int, shots, grad_out, n_checkpoints: int = 0,
+                    hbm_budget_bytes: int = 0, stream=None) -> float:
+    """shots: sequence of (src_xyz, src_wav, rec_xyz, d_obs, d_pred or None).
+    Returns the summed misfit; grad_out receives the summed gradient."""
+    arr = (wf_shot * len(shots))()
+    keep = []
+    for i, (sxyz, wav, rxyz, dob, dpred) in enumerate(shots):
+        ns, sp, sa = _host(sxyz)
+        nr, rp, ra = _host(rxyz)
+        keep += [sa, ra]
+        arr[i] = wf_shot(ns, sp, _ptr(wav) if ns else None, nr, rp, _ptr(dob) if nr else None,
+                         _ptr(dpred) if (dpred is not None and nr) else None)
+    phi = ctypes.c_double()
+    _check(lib.wf_fwi_gradient(model, float(dt), int(nt), len(shots), arr, _ptr(grad_out),
+                               ctypes.byref(phi), int(n_checkpoints), int(hbm_budget_bytes),
+                               _stream(stream)))
+    del keep
+    return float(phi.value)
+
+
+def wf_model_update(model, grad, alpha: float, m_lo: float, m_hi: float = float("inf"),
+                    m_out=None, stream=None):
+    _check(lib.wf_model_update(model, _ptr(grad), float(alpha), float(m_lo), float(m_hi),
+                               _ptr(m_out), _stream(stream)))
 
 
 def wf_revolve_forward_steps(steps: int, snaps: int) -> int:

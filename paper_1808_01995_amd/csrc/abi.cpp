@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "runtime.h"
 
@@ -92,6 +93,17 @@ int64_t wf_model_bytes(const wf_model* model) {
     return static_cast<const Model*>(model)->bytes();
 }
 
+wf_status wf_model_trim(wf_model* model) {
+    ABI_GUARD_BEGIN
+    if (!model) return fail(WF_E_ARG, "model is NULL");
+    Model& md = *as_model(model);
+    wf_status st = hip_check(hipStreamSynchronize(md.last_stream), "sync");
+    if (st != WF_OK) return st;
+    md.ws.reset();
+    return WF_OK;
+    ABI_GUARD_END
+}
+
 wf_status wf_graph_enable(int on) {
     set_graphs_enabled(on != 0);
     return WF_OK;
@@ -165,6 +177,45 @@ wf_status wf_gradient(wf_model* model, double dt, int nt, int nsrc, const double
     if ((st = md.points(nrec, rec_xyz, &rec)) != WF_OK) return st;
     return run_gradient(md, dt, nt, *src, src_wav, *rec, residual, grad_out, n_checkpoints,
                         hbm_budget_bytes, as_stream(stream));
+    ABI_GUARD_END
+}
+
+wf_status wf_fwi_gradient(wf_model* model, double dt, int nt, int nshots, const wf_shot* shots,
+                          float* grad_out, double* misfit_out, int n_checkpoints,
+                          int64_t hbm_budget_bytes, void* stream) {
+    ABI_GUARD_BEGIN
+    if (!model) return fail(WF_E_ARG, "model is NULL");
+    Model& md = *as_model(model);
+    if (nt < 1) return fail(WF_E_ARG, "nt must be >= 1");
+    if (nshots < 1 || !shots) return fail(WF_E_ARG, "at least one shot is needed");
+    if (!grad_out) return fail(WF_E_ARG, "grad_out is NULL");
+    if (n_checkpoints < -1) return fail(WF_E_ARG, "n_checkpoints must be >= -1");
+    if (hbm_budget_bytes < 0) return fail(WF_E_ARG, "negative budget");
+    wf_status st;
+    if ((st = md.check_dt(dt)) != WF_OK) return st;
+    std::vector<FwiShot> v((size_t)nshots);
+    for (int i = 0; i < nshots; ++i) {
+        const wf_shot& sh = shots[i];
+        if ((st = check_series(nt, sh.nsrc, sh.src_wav, "src_wav")) != WF_OK) return st;
+        if ((st = check_series(nt, sh.nrec, sh.d_obs, "d_obs")) != WF_OK) return st;
+        if (sh.nsrc > 0 && !sh.src_xyz) return fail(WF_E_ARG, "shot %d: src_xyz is NULL", i);
+        if (sh.nrec > 0 && !sh.rec_xyz) return fail(WF_E_ARG, "shot %d: rec_xyz is NULL", i);
+        // every coordinate is checked before any work is enqueued
+        const PointSet* ps = nullptr;
+        if ((st = md.points(sh.nsrc, sh.src_xyz, &ps)) != WF_OK) return st;
+        if ((st = md.points(sh.nrec, sh.rec_xyz, &ps)) != WF_OK) return st;
+        v[(size_t)i] = FwiShot{sh.nsrc, sh.src_xyz, sh.src_wav, sh.nrec, sh.rec_xyz, sh.d_obs, sh.d_pred};
+    }
+    return run_fwi_gradient(md, dt, nt, v, grad_out, misfit_out, n_checkpoints, hbm_budget_bytes,
+                            as_stream(stream));
+    ABI_GUARD_END
+}
+
+wf_status wf_model_update(wf_model* model, const float* grad, double alpha, double m_lo,
+                          double m_hi, float* m_out, void* stream) {
+    ABI_GUARD_BEGIN
+    if (!model) return fail(WF_E_ARG, "model is NULL");
+    return as_model(model)->update(grad, alpha, m_lo, m_hi, m_out, as_stream(stream));
     ABI_GUARD_END
 }
 

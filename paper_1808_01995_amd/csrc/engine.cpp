@@ -211,13 +211,15 @@ static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
         j->foot = model + inc_src + tables;
         j->small = L.npoints <= kSmallPoints;
     } else {
-        // forward record + residual, both increment tables, adjoint pair and
-        // gradient, and a checkpoint pool of up to 2*32+3 fields (store-all if it fits)
+        // record scratch (predicted data, residual, partial sums), both
+        // increment tables, adjoint pair and gradient, and a checkpoint pool of
+        // up to 2*32+3 fields (store-all if it fits)
         const int64_t l = r->nt - 1;
-        const int64_t fixed = model + inc_src + inc_rec + (int64_t)r->nt * r->nrec * 4 + 3 * fb + tables;
+        const int64_t rec_bytes = 2 * (int64_t)r->nt * r->nrec * 4 + ((int64_t)1 << 20);
+        const int64_t fixed = model + inc_src + inc_rec + rec_bytes + 3 * fb + tables;
         int64_t pool = std::min<int64_t>(l + 1, 2 * 32 + 3) * fb;
         if (fixed + pool > budget) pool = 5 * fb;   // one snapshot, the minimum
-        j->grad_cap = 3 * fb + pool + ((int64_t)1 << 20);
+        j->grad_cap = 3 * fb + pool + rec_bytes + ((int64_t)1 << 20);
         j->foot = fixed + pool;
         j->small = false;
     }
@@ -239,25 +241,11 @@ void wf_engine::run_large(EJob* j, hipStream_t s) {
         st = run_forward(*md, r.dt, r.nt, *src, r.src_wav, *rec, r.rec_out, nullptr, 1, s);
         if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
     } else if (st == WF_OK) {
-        const int64_t n = (int64_t)r.nt * r.nrec;
-        DevBuf res, part;
-        st = res.alloc(n * 4 + 256);
-        if (st == WF_OK) st = part.alloc((int64_t)residual_blocks(n) * 8 + 256);
-        if (st == WF_OK) st = run_forward(*md, r.dt, r.nt, *src, r.src_wav, *rec, res.f(), nullptr, 1, s);
-        if (st == WF_OK && r.rec_out)
-            st = hip_check(launch_copy(res.f(), r.rec_out, n, s), "copy record");
-        if (st == WF_OK && n > 0) {
-            std::vector<double> ph((size_t)residual_blocks(n));
-            st = hip_check(launch_residual(res.f(), r.d_obs, res.f(), n, part.as<double>(), s), "residual");
-            if (st == WF_OK)
-                st = hip_check(hipMemcpyAsync(ph.data(), part.ptr, ph.size() * 8, hipMemcpyDeviceToHost, s), "misfit");
-            if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
-            double phi = 0.0;
-            for (double v : ph) phi += v;
-            if (st == WF_OK && r.misfit_out) *r.misfit_out = 0.5 * phi;
-        }
-        if (st == WF_OK)
-            st = run_gradient(*md, r.dt, r.nt, *src, r.src_wav, *rec, res.f(), r.grad_out, 0, j->grad_cap, s);
+        // two wave solves: the residual comes from the gradient's own forward sweep
+        double phi = 0.0;
+        st = run_gradient(*md, r.dt, r.nt, *src, r.src_wav, *rec, nullptr, r.grad_out, 0, j->grad_cap, s,
+                          r.d_obs, r.rec_out, &phi);
+        if (st == WF_OK && r.misfit_out) *r.misfit_out = phi;
         if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
     }
     delete md;   // waits for the model's stream

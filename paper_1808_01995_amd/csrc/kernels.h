@@ -155,6 +155,9 @@ hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count
 int residual_blocks(int64_t n);
 hipError_t launch_residual(const float* d, const float* d_obs, float* r, int64_t n, double* partial,
                            hipStream_t s);
+// m[i] = min(max(m[i] - alpha g[i], lo), hi) (one rounding: fma)
+hipError_t launch_update(float* m, const float* g, float alpha, float lo, float hi, int64_t n,
+                         hipStream_t s);
 // min and max of m over n values into out[0], out[1] (out pre-filled by caller)
 hipError_t launch_minmax(const float* x, int64_t n, float* out2, hipStream_t s);
 

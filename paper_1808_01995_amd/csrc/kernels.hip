@@ -527,6 +527,13 @@ __global__ void k_minmax(const float* __restrict__ x, int64_t n, unsigned int* o
     if (bad) atomicAdd(&out3[2], bad);
 }
 
+__global__ void k_update(float* __restrict__ m, const float* __restrict__ g, float alpha, float lo,
+                         float hi, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m[i] = fminf(fmaxf(fmaf(-alpha, g[i], m[i]), lo), hi);
+}
+
 unsigned rows_grid(int nx, int ny) {
     return (unsigned)std::min<int64_t>((int64_t)nx * ny, 65535);
 }
@@ -774,6 +781,13 @@ hipError_t launch_residual(const float* d, const float* d_obs, float* r, int64_t
 hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_1d(n, 256)), dim3(256), 0, s, x, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(float* m, const float* g, float alpha, float lo, float hi, int64_t n,
+                         hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update, dim3(grid_1d(n, 256)), dim3(256), 0, s, m, g, alpha, lo, hi, n);
     return hipGetLastError();
 }
 

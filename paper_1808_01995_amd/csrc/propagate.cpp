@@ -336,26 +336,50 @@ namespace {
 // A pool of pitched field buffers (with zero ghost planes) carved from one
 // allocation, zeroed once.
 struct FieldPool {
-    DevBuf mem;
+    DevBuf own;
+    float* base = nullptr;
     int64_t stride = 0;   // floats per buffer
     int64_t off = 0;      // plane 0 within a buffer
     int count = 0;
-    wf_status alloc(const Layout& L, int n, hipStream_t s) {
+    static int64_t bytes_for(const Layout& L, int n) {
+        return (int64_t)n * ((L.alloc_elems + 63) / 64 * 64) * 4 + 256;
+    }
+    // n zeroed buffers in `buf` (grown if too small; work enqueued on s before
+    // this call may still read the old contents, so growing waits for it)
+    wf_status carve(DevBuf& buf, const Layout& L, int n, hipStream_t s) {
         stride = (L.alloc_elems + 63) / 64 * 64;
         off = L.ghost_off;
         count = n;
-        wf_status st = mem.alloc((int64_t)n * stride * 4 + 256);
-        if (st != WF_OK) return st;
-        return hip_check(launch_fill(mem.f(), mem.bytes / 4, 0.0f, s), "fill");
+        const int64_t need = bytes_for(L, n);
+        if (buf.bytes < need) {
+            wf_status st = hip_check(hipStreamSynchronize(s), "sync");
+            if (st == WF_OK) {
+                buf.reset();
+                st = buf.alloc(need);
+            }
+            if (st != WF_OK) return st;
+        }
+        base = buf.f();
+        return hip_check(launch_fill(base, need / 4, 0.0f, s), "fill");
     }
-    float* at(int i) const { return mem.f() + (int64_t)i * stride + off; }
+    wf_status alloc(const Layout& L, int n, hipStream_t s) { return carve(own, L, n, s); }
+    float* at(int i) const { return base + (int64_t)i * stride + off; }
 };
 
 }  // namespace
 
-wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
-                       const PointSet& rec, const float* residual, float* grad_out, int n_ck,
-                       int64_t budget, hipStream_t s) {
+namespace {
+
+// One shot's adjoint-state gradient added into the pitched accumulator G.
+// With `obs`, the residual is formed inside the call: the first forward sweep
+// samples d = P_r u into obs->d_pred, and before the first reverse step
+// r = d - d_obs goes to obs->resid with the FP64 partial sums of |r|^2 in
+// obs->partial (two wave solves per shot). Otherwise `residual` is given.
+// `held` bytes (the accumulator and the record scratch, allocated by the
+// caller) count against the budget.
+wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                        const PointSet& rec, const float* residual, const ObsData* obs, float* G,
+                        int64_t held, int n_ck, int64_t budget, hipStream_t s) {
     const Layout& L = md.L;
     const int64_t fb = ((L.alloc_elems + 63) / 64 * 64) * 4;
     WF_TRY(md.ensure_kap(dt, s));
@@ -363,15 +387,22 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
     md.fill_step(p, dt);
     md.fill_step(pi, dt, true);
     const int64_t l = nt - 1;                     // adjoint steps n = 0..nt-2
+    const int64_t nrec = rec.npts;
     if (l <= 0) {
-        return hip_check(launch_fill(grad_out, L.npoints, 0.0f, s), "fill");
+        // one sample: u^0 = 0, so d^0 = 0 and the gradient has no term
+        if (obs && nrec > 0) {
+            WF_TRY(hip_check(launch_fill(obs->d_pred, nrec, 0.0f, s), "fill"));
+            WF_TRY(hip_check(launch_residual(obs->d_pred, obs->d_obs, obs->resid, nrec, obs->partial, s),
+                             "residual"));
+        }
+        return WF_OK;
     }
-    // memory plan: adjoint pair + gradient accumulator (3 fields) plus either
-    // every forward field (store-all: nt fields incl. one zero field) or a
-    // revolve pool of 2 s + 3 fields
-    int64_t cap = device_free_bytes();
+    // memory plan: adjoint pair + what the caller holds (accumulator, record
+    // scratch) plus either every forward field (store-all: nt fields incl. one
+    // zero field) or a revolve pool of 2 s + 3 fields
+    int64_t cap = device_free_bytes() + held + md.ws.bytes;   // the workspace is reused
     if (budget > 0) cap = std::min<int64_t>(cap, budget);
-    const int64_t fixed = 3 * fb;
+    const int64_t fixed = 2 * fb + held;
     bool store_all = false;
     int snaps = n_ck;
     if (n_ck == -1) {
@@ -391,25 +422,47 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
     const int64_t need = fixed + (int64_t)nbuf * fb;
     if (need > cap) return fail(WF_E_BUDGET, "gradient needs %lld bytes, %lld available", (long long)need, (long long)cap);
 
-    FieldPool adj;
-    WF_TRY(adj.alloc(L, 3, s));
-    float* V1 = adj.at(0);   // v^{n+1}
-    float* V2 = adj.at(1);   // v^{n+2}, overwritten by v^n
-    float* G = adj.at(2);    // gradient accumulator (pitched)
+    // one carve of the model's workspace (kept for the next call: allocating
+    // tens of GB again costs seconds) holds the pool and the adjoint pair
     FieldPool pool;
-    WF_TRY(pool.alloc(L, nbuf, s));
+    WF_TRY(pool.carve(md.ws, L, nbuf + 2, s));
+    float* V1 = pool.at(nbuf);       // v^{n+1}
+    float* V2 = pool.at(nbuf + 1);   // v^{n+2}, overwritten by v^n
     Injector qinj, rinj;   // sources in forward steps, residual in adjoint steps
     WF_TRY(qinj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
-    WF_TRY(rinj.prepare(md, rec, pi, residual, nt, md.d_inc[1], s));
+    bool resid_ready = obs == nullptr;
+    if (resid_ready) WF_TRY(rinj.prepare(md, rec, pi, residual, nt, md.d_inc[1], s));
+    int64_t next_row = 0;   // first record row not yet sampled (observed-data mode)
 
-    // forward step n: u^{n+1} into `out` from u^n, u^{n-1}, injecting q^n
+    // forward step n: u^{n+1} into `out` from u^n, u^{n-1}, injecting q^n;
+    // on the first sweep (observed-data mode) it also samples d^n = P_r u^n
     auto forward_step = [&](int64_t n, const float* cur, const float* old, float* out) -> wf_status {
         qinj.configure(p, n);
+        if (obs && n == next_row) {
+            set_sampling(p, &rec, nrec ? obs->d_pred + n * nrec : nullptr);
+            ++next_row;
+        } else {
+            set_sampling(p, nullptr, nullptr);
+        }
         WF_TRY(step(p, md, cur, old, out, false, nullptr, nullptr, s));
         return qinj.after(md, n, out, nullptr, nullptr, p, s);
     };
+    // before the first reverse step: the last record row and the residual
+    auto form_residual = [&](const float* u_last) -> wf_status {
+        if (resid_ready) return WF_OK;
+        if (next_row != l) return fail(WF_E_STATE, "record incomplete before the reverse sweep");
+        if (nrec > 0) {
+            WF_TRY(sample(rec, u_last, obs->d_pred + l * nrec, s));
+            WF_TRY(hip_check(launch_residual(obs->d_pred, obs->d_obs, obs->resid, (int64_t)nt * nrec,
+                                             obs->partial, s), "residual"));
+        }
+        WF_TRY(rinj.prepare(md, rec, pi, obs->resid, nt, md.d_inc[1], s));
+        resid_ready = true;
+        return WF_OK;
+    };
     // adjoint step n with imaging of term j = n+1 (u^{n+1} given)
     auto reverse_step = [&](int64_t n, const float* u_np1) -> wf_status {
+        WF_TRY(form_residual(u_np1));
         rinj.configure(pi, n + 1);
         WF_TRY(step(pi, md, V1, V2, V2, true, G, u_np1, s));
         WF_TRY(rinj.after(md, n + 1, V2, G, u_np1, pi, s));
@@ -480,8 +533,95 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
             }
         }
     }
-    WF_TRY(hip_check(launch_unpitch(G, grad_out, L.nx, L.ny, L.nz, L.sx, L.sy, s), "unpitch"));
     // the pools are freed when this returns; wait for the work that reads them
+    return hip_check(hipStreamSynchronize(s), "sync");
+}
+
+// Scratch of the observed-data mode for records of up to n = nt * nrec values.
+struct ObsScratch {
+    DevBuf pred, res, part;
+    std::vector<double> host;
+    wf_status ensure(int64_t n) {
+        const int64_t nb = residual_blocks(std::max<int64_t>(n, 1));
+        if (pred.bytes < n * 4) WF_TRY(pred.alloc(std::max<int64_t>(n, 1) * 4));
+        if (res.bytes < n * 4) WF_TRY(res.alloc(std::max<int64_t>(n, 1) * 4));
+        if (part.bytes < nb * 8) WF_TRY(part.alloc(nb * 8));
+        return WF_OK;
+    }
+    int64_t bytes() const { return pred.bytes + res.bytes + part.bytes; }
+    // 1/2 |r|^2 from the partial sums
+    wf_status misfit(int64_t n, hipStream_t s, double* out) {
+        *out = 0.0;
+        if (n <= 0) return WF_OK;
+        host.assign((size_t)residual_blocks(n), 0.0);
+        WF_TRY(hip_check(hipMemcpyAsync(host.data(), part.ptr, host.size() * 8, hipMemcpyDeviceToHost, s),
+                         "read misfit"));
+        WF_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+        double phi = 0.0;
+        for (double v : host) phi += v;   // fixed order: deterministic
+        *out = 0.5 * phi;
+        return WF_OK;
+    }
+};
+
+}  // namespace
+
+wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                       const PointSet& rec, const float* residual, float* grad_out, int n_ck,
+                       int64_t budget, hipStream_t s, const float* d_obs, float* d_pred_out,
+                       double* misfit_out) {
+    const Layout& L = md.L;
+    FieldPool acc;
+    WF_TRY(acc.alloc(L, 1, s));   // zeroed accumulator
+    ObsScratch sc;
+    ObsData obs;
+    const int64_t n = (int64_t)nt * rec.npts;
+    if (d_obs) {
+        WF_TRY(sc.ensure(n));
+        obs.d_obs = d_obs;
+        obs.d_pred = d_pred_out ? d_pred_out : sc.pred.f();
+        obs.resid = sc.res.f();
+        obs.partial = sc.part.as<double>();
+    }
+    WF_TRY(gradient_core(md, dt, nt, src, src_wav, rec, residual, d_obs ? &obs : nullptr, acc.at(0),
+                         acc.own.bytes + sc.bytes(), n_ck, budget, s));
+    WF_TRY(hip_check(launch_unpitch(acc.at(0), grad_out, L.nx, L.ny, L.nz, L.sx, L.sy, s), "unpitch"));
+    if (d_obs) {
+        double phi = 0.0;
+        WF_TRY(sc.misfit(n, s, &phi));
+        if (misfit_out) *misfit_out = phi;
+    }
+    return hip_check(hipStreamSynchronize(s), "sync");
+}
+
+wf_status run_fwi_gradient(Model& md, double dt, int nt, const std::vector<FwiShot>& shots,
+                           float* grad_out, double* misfit_out, int n_ck, int64_t budget,
+                           hipStream_t s) {
+    const Layout& L = md.L;
+    FieldPool acc;
+    WF_TRY(acc.alloc(L, 1, s));   // the sum over shots, zeroed once
+    ObsScratch sc;
+    int64_t nmax = 0;
+    for (const FwiShot& sh : shots) nmax = std::max<int64_t>(nmax, (int64_t)nt * sh.nrec);
+    WF_TRY(sc.ensure(nmax));
+    double phi = 0.0;
+    for (const FwiShot& sh : shots) {
+        const PointSet *src = nullptr, *rec = nullptr;
+        WF_TRY(md.points(sh.nsrc, sh.src_xyz, &src));
+        WF_TRY(md.points(sh.nrec, sh.rec_xyz, &rec));
+        ObsData obs;
+        obs.d_obs = sh.d_obs;
+        obs.d_pred = sh.d_pred ? sh.d_pred : sc.pred.f();
+        obs.resid = sc.res.f();
+        obs.partial = sc.part.as<double>();
+        WF_TRY(gradient_core(md, dt, nt, *src, sh.src_wav, *rec, nullptr, &obs, acc.at(0),
+                             acc.own.bytes + sc.bytes(), n_ck, budget, s));
+        double ph = 0.0;
+        WF_TRY(sc.misfit((int64_t)nt * sh.nrec, s, &ph));
+        phi += ph;
+    }
+    WF_TRY(hip_check(launch_unpitch(acc.at(0), grad_out, L.nx, L.ny, L.nz, L.sx, L.sy, s), "unpitch"));
+    if (misfit_out) *misfit_out = phi;
     return hip_check(hipStreamSynchronize(s), "sync");
 }
 

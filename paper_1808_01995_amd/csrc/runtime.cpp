@@ -3,6 +3,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -260,6 +261,12 @@ wf_status build_points(const wf_geom* g, const Layout& L, int npts, const double
     return WF_OK;
 }
 
+#define WF_TRY_RT(expr)                      \
+    do {                                     \
+        wf_status st__ = (expr);             \
+        if (st__ != WF_OK) return st__;      \
+    } while (0)
+
 static std::atomic<int64_t> g_pointset_gen{1};
 
 wf_status PointSet::build(const wf_geom* g, const Layout& L, int npts_, const double* xyz) {
@@ -445,7 +452,13 @@ wf_status Model::set_m(const float* m_dev, hipStream_t s) {
     if ((st = hip_check(hipMemcpyAsync(d_m.f(), m_dev, (size_t)L.npoints * 4,
                                        hipMemcpyDeviceToDevice, s), "copy m")) != WF_OK)
         return st;
-    // min / max of m (for the stability check) and validity of every value
+    return refresh_m(s);
+}
+
+// min / max of m (for the stability check) and validity of every value;
+// invalidates the coefficients
+wf_status Model::refresh_m(hipStream_t s) {
+    wf_status st;
     unsigned int init3[3] = {0x7f7fffffu, 0u, 0u};
     unsigned int* d3 = reinterpret_cast<unsigned int*>(d_scratch.ptr);
     if ((st = hip_check(hipMemcpyAsync(d3, init3, sizeof init3, hipMemcpyHostToDevice, s), "init minmax")) != WF_OK)
@@ -464,6 +477,31 @@ wf_status Model::set_m(const float* m_dev, hipStream_t s) {
     m_max = hi;
     kap_dt = -1.0;   // coefficients must be recomputed
     return WF_OK;
+}
+
+wf_status Model::update(const float* grad, double alpha, double lo, double hi, float* m_out,
+                        hipStream_t s) {
+    if (!grad) return fail(WF_E_ARG, "grad is NULL");
+    if (!std::isfinite(alpha)) return fail(WF_E_ARG, "alpha must be finite");
+    if (!(lo > 0.0) || !std::isfinite(lo) || !(hi >= lo))
+        return fail(WF_E_ARG, "bounds must satisfy 0 < m_lo <= m_hi");
+    const float flo = (float)lo;
+    const float fhi = hi >= (double)FLT_MAX ? FLT_MAX : (float)hi;
+    if (!(flo > 0.0f) || !(fhi >= flo)) return fail(WF_E_ARG, "bounds are not representable in FP32");
+    last_stream = s;
+    // a non-finite gradient value would be clamped silently: refuse it first
+    unsigned int* cnt = reinterpret_cast<unsigned int*>(d_scratch.ptr);
+    unsigned int bad = 0;
+    WF_TRY_RT(hip_check(hipMemsetAsync(cnt, 0, 4, s), "clear"));
+    WF_TRY_RT(hip_check(launch_count_nonfinite(grad, L.npoints, cnt, s), "check grad"));
+    WF_TRY_RT(hip_check(hipMemcpyAsync(&bad, cnt, 4, hipMemcpyDeviceToHost, s), "read"));
+    WF_TRY_RT(hip_check(hipStreamSynchronize(s), "sync"));
+    if (bad) return fail(WF_E_NONFINITE, "grad has %u values that are not finite", bad);
+    WF_TRY_RT(hip_check(launch_update(d_m.f(), grad, (float)alpha, flo, fhi, L.npoints, s), "update"));
+    if (m_out)
+        WF_TRY_RT(hip_check(hipMemcpyAsync(m_out, d_m.f(), (size_t)L.npoints * 4, hipMemcpyDeviceToDevice, s),
+                            "copy m"));
+    return refresh_m(s);
 }
 
 double Model::vmax() const { return 1.0 / std::sqrt(m_min); }

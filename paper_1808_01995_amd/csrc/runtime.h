@@ -126,6 +126,7 @@ struct Model : public wf_model {
     double alpha[wf::kMaxHalf + 1]{};
     wf::DevBuf d_m, d_kap, d_u[2], d_etax, d_etay, d_etaz, d_scratch;
     wf::DevBuf d_inc[2];   // precomputed injection increments (grow-only, stream-ordered reuse)
+    wf::DevBuf ws;         // gradient workspace (checkpoint pool + adjoint pair), kept between calls
     float m_min = 0.f, m_max = 0.f;
     double kap_dt = -1.0;
     std::vector<PCache> pcache;
@@ -152,6 +153,9 @@ struct Model : public wf_model {
     ~Model() override;
     wf_status init(const wf_geom* g, const float* m_dev, hipStream_t s);
     wf_status set_m(const float* m_dev, hipStream_t s);
+    wf_status refresh_m(hipStream_t s);
+    // m <- min(max(m - alpha grad, lo), hi); m_out (optional) receives it
+    wf_status update(const float* grad, double alpha, double lo, double hi, float* m_out, hipStream_t s);
     wf_status ensure_kap(double dt, hipStream_t s);
     wf_status check_dt(double dt) const;
     double vmax() const;
@@ -162,7 +166,7 @@ struct Model : public wf_model {
     float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
         return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_etax.bytes + d_etay.bytes +
-               d_etaz.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes;
+               d_etaz.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes + ws.bytes;
     }
 };
 
@@ -186,9 +190,38 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
                       hipStream_t s);
 wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const float* rec_in,
                       const PointSet& src, float* src_out, hipStream_t s);
+// Adjoint-state gradient (dense grad_out, overwritten). With d_obs (device
+// [nt][nrec]) the residual is formed from the call's own forward sweep
+// (residual ignored): d_pred_out (optional) receives P_r u and misfit_out
+// 1/2 |P_r u - d_obs|^2.
 wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                        const PointSet& rec, const float* residual, float* grad_out, int n_ck,
-                       int64_t budget, hipStream_t s);
+                       int64_t budget, hipStream_t s, const float* d_obs = nullptr,
+                       float* d_pred_out = nullptr, double* misfit_out = nullptr);
+
+// Observed-data terms of one gradient sweep (device buffers [nt][nrec]).
+struct ObsData {
+    const float* d_obs = nullptr;
+    float* d_pred = nullptr;    // receives P_r u
+    float* resid = nullptr;     // receives P_r u - d_obs
+    double* partial = nullptr;  // residual_blocks(nt nrec) FP64 partial sums of resid^2
+};
+
+// One source experiment of a multi-shot gradient (host coordinates; the
+// point tables are looked up shot by shot, so any number of shots fits the
+// model's table cache).
+struct FwiShot {
+    int nsrc = 0;
+    const double* src_xyz = nullptr;
+    const float* src_wav = nullptr;
+    int nrec = 0;
+    const double* rec_xyz = nullptr;
+    const float* d_obs = nullptr;
+    float* d_pred = nullptr;    // optional
+};
+wf_status run_fwi_gradient(Model& md, double dt, int nt, const std::vector<FwiShot>& shots,
+                           float* grad_out, double* misfit_out, int n_ck, int64_t budget,
+                           hipStream_t s);
 
 // Batched forward shots (serving engine): a grid advanced by k_step_batch
 // launches shared with other grids. begin() prepares fields, coefficients,

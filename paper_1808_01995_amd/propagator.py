@@ -91,6 +91,10 @@ class Propagator:
         except Exception:
             pass
 
+    def trim(self):
+        """Free the gradient workspace the model keeps between calls."""
+        _abi.wf_model_trim(self.handle)
+
     def set_m(self, m: torch.Tensor):
         m = m.to(device=self.device, dtype=torch.float32).contiguous()
         if tuple(m.shape) != self.comp_shape:
@@ -150,6 +154,39 @@ class Propagator:
         _abi.wf_gradient(self.handle, dt, nt, src_xyz, q, rec_xyz, r, g, n_checkpoints,
                          hbm_budget_bytes)
         return g
+
+
+    def fwi_gradient(self, dt: float, nt: int, shots, n_checkpoints: int = 0,
+                     hbm_budget_bytes: int = 0, return_pred: bool = False):
+        """Multi-shot FWI objective and gradient at the current m: shots is a
+        sequence of (src_xyz, src_wav [nt, nsrc], rec_xyz, d_obs [nt, nrec]).
+        Returns (misfit, gradient on the computational grid) and, with
+        return_pred, the predicted records."""
+        marsh, preds = [], []
+        for sxyz, wav, rxyz, dob in shots:
+            sxyz = np.atleast_2d(np.asarray(sxyz, dtype=np.float64))
+            rxyz = np.atleast_2d(np.asarray(rxyz, dtype=np.float64))
+            q = self._series(wav, nt, sxyz.shape[0], "src_wav")
+            d = self._series(dob, nt, rxyz.shape[0], "d_obs")
+            dp = torch.empty_like(d) if return_pred else None
+            preds.append(dp)
+            marsh.append((sxyz, q, rxyz, d, dp))
+        g = torch.empty(self.comp_shape, dtype=torch.float32, device=self.device)
+        phi = _abi.wf_fwi_gradient(self.handle, dt, nt, marsh, g, n_checkpoints, hbm_budget_bytes)
+        return (phi, g, preds) if return_pred else (phi, g)
+
+    def update(self, grad: torch.Tensor, alpha: float, vmin: Optional[float] = None,
+               vmax: Optional[float] = None):
+        """Fixed-step update m <- m - alpha grad, with the velocity kept in
+        [vmin, vmax] (as bounds 1/vmax^2 <= m <= 1/vmin^2)."""
+        grad = grad.to(device=self.device, dtype=torch.float32).contiguous()
+        if tuple(grad.shape) != self.comp_shape:
+            raise ValueError("grad has shape %s, expected %s" % (tuple(grad.shape), self.comp_shape))
+        m_lo = 1.0 / vmax ** 2 if vmax else float(np.finfo(np.float32).tiny)
+        m_hi = 1.0 / vmin ** 2 if vmin else float("inf")
+        m = torch.empty_like(self.m)
+        _abi.wf_model_update(self.handle, grad, alpha, m_lo, m_hi, m)
+        self.m = m
 
 
 class ModelingFunction(torch.autograd.Function):

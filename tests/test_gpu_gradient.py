@@ -129,3 +129,23 @@ def test_autograd_function_matches_gradient():
     m2 = torch.zeros(P.shape_phys, device="cuda", dtype=torch.float64, requires_grad=True)
     (pad_replicate(m2, P.nbl) * g_comp.double()).sum().backward()
     assert rel_l2(m_phys.grad.double().cpu().numpy(), m2.grad.cpu().numpy()) < 1e-5
+
+
+def test_gradient_workspace_kept_and_trimmed():
+    """The checkpoint pool stays with the model between gradient calls (no
+    reallocation) and wf_model_trim frees it; results do not change."""
+    from paper_1808_01995_amd import _abi
+    P, Pt = _anomaly_problem(n=20, steps=40)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    r = torch.ones((P.nt, P.rec_xyz.shape[0]), device="cuda")
+    b0 = _abi.wf_model_bytes(prop.handle)
+    g1 = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    b1 = _abi.wf_model_bytes(prop.handle)
+    assert b1 >= b0 + P.nt * prop.npoints * 4
+    g2 = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=5)   # smaller: reused
+    assert _abi.wf_model_bytes(prop.handle) == b1
+    prop.trim()
+    assert _abi.wf_model_bytes(prop.handle) < b1
+    g3 = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    assert torch.equal(g1, g2) and torch.equal(g1, g3)
