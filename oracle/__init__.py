@@ -54,6 +54,7 @@ __all__ = [
     "build", "fd_weights", "fd_weights_float", "abs_weight_sum", "critical_dt",
     "pad_edge", "damping_eta", "sparse_points", "Grid", "laplacian", "step",
     "forward", "adjoint", "gradient", "energy", "misfit", "fwi_objective", "fwi_update",
+    "born",
 ]
 
 
@@ -401,6 +402,37 @@ def gradient(grid: Grid, m: np.ndarray, eta: np.ndarray, dt: float, nt: int,
     if rc != 0:
         raise MemoryError("oracle_gradient")
     return (g1, g2) if both else g1
+
+
+def born(grid: Grid, m: np.ndarray, eta: np.ndarray, dt: float, nt: int,
+         src, q: np.ndarray, rec, dm: np.ndarray) -> np.ndarray:
+    """Linearised (Born) modelling dd = J dm, J the Jacobian of the discrete
+    forward map m -> P_r u(m) whose transpose the adjoint-state gradient
+    applies (eq. Grad). Differentiating the update
+        a u^{n+1} = 2 m u^n - b u^{n-1} + dt^2 L u^n + dt^2 P_s^T q^n,
+        a = m + eta dt/2, b = m - eta dt/2 (eta independent of m),
+    in direction dm gives the scattered field
+        a du^{n+1} = 2 m du^n - b du^{n-1} + dt^2 L du^n - dm (u^{n+1} - 2 u^n + u^{n-1}),
+    du^0 = du^{-1} = 0, dd^n = P_r du^n, u the background field of forward().
+    Returns dd [nt, nrec]."""
+    m = np.asarray(m, dtype=np.float64)
+    dm = np.asarray(dm, dtype=np.float64)
+    eta = np.ascontiguousarray(eta, dtype=np.float64)
+    _, us = forward(grid, m, eta, dt, nt, src, q, rec, save=True)
+    a = m + 0.5 * eta * dt
+    node, w = rec
+    node = np.atleast_2d(np.asarray(node, dtype=np.int64))
+    w = np.atleast_2d(np.asarray(w, dtype=np.float64))
+    dd = np.zeros((nt, node.shape[0]))
+    du_prev = np.zeros(grid.shape)
+    du = np.zeros(grid.shape)
+    zero = np.zeros(grid.shape)
+    for n in range(nt - 1):
+        u_prev = us[n - 1] if n >= 1 else zero
+        du_next = step(grid, m, eta, dt, du_prev, du) - (dm / a) * (us[n + 1] - 2.0 * us[n] + u_prev)
+        dd[n + 1] = np.sum(w * du_next.ravel()[node], axis=1)
+        du_prev, du = du, du_next
+    return dd
 
 
 def fwi_objective(grid: Grid, m: np.ndarray, eta: np.ndarray, dt: float, nt: int,
