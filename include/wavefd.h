@@ -223,6 +223,22 @@ wf_status wf_fwi_gradient(wf_model* model, double dt, int nt, int nshots, const 
 wf_status wf_model_update(wf_model* model, const float* grad, double alpha, double m_lo,
                           double m_hi, float* m_out, void* stream);
 
+/* Linearised (Born) modelling dd = J dm, J the Jacobian of the forward map
+ * m -> P_r u(m) (the operator whose transpose the gradient applies, eq. Grad):
+ * the scattered field du solves the update of wf_forward driven by the
+ * source -dm (u^{n+1} - 2 u^n + u^{n-1}) / dt^2 (injected with weight dt^2/a
+ * on every node), du^0 = 0, dd^n = P_r du^n.
+ *   dm       device FP32 Nc^D (dense): squared-slowness perturbation
+ *   drec_out device FP32 [nt][nrec] (written)
+ *   rec_out  device FP32 [nt][nrec] or NULL: the background record P_r u
+ * Other arguments as in wf_forward. wf_gradient with residual r applies the
+ * exact transpose: <J dm, r> = <dm, J^T r> to rounding. With the observed
+ * data as the residual, wf_gradient gives the reverse-time-migration image
+ * J^T d. Synchronises `stream` (it frees its scratch fields). */
+wf_status wf_born(wf_model* model, double dt, int nt,
+                  int nsrc, const double* src_xyz, const float* src_wav, const float* dm,
+                  int nrec, const double* rec_xyz, float* drec_out, float* rec_out, void* stream);
+
 /* Number of forward time steps the revolve schedule of wf_gradient performs
  * for `steps` updates and `snaps` stored states (steps >= 1, snaps >= 1):
  * the optimal count r l - C(s + r, r - 1) of Griewank and Walther. Pure host

@@ -106,6 +106,7 @@ def _load():
         "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
         "wf_gradient": (I, [P, D, I, I, P, P, I, P, P, P, I, I64, P]),
         "wf_fwi_gradient": (I, [P, D, I, I, ctypes.POINTER(wf_shot), P, P, I, I64, P]),
+        "wf_born": (I, [P, D, I, I, P, P, P, I, P, P, P, P]),
         "wf_model_update": (I, [P, P, D, D, D, P, P]),
         "wf_revolve_forward_steps": (I64, [I64, I]),
         "wf_profile_enable": (I, [I]),
@@ -130,7 +131,7 @@ EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf
            "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches", "wf_graph_enable",
            "wf_model_trim",
            "wf_model_destroy", "wf_forward", "wf_adjoint",
-           "wf_gradient", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
+           "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
            "wf_engine_create", "wf_engine_submit",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
 
@@ -266,6 +267,15 @@ def wf_gradient(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, residual, 
     _check(lib.wf_gradient(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None,
                            nr, rp, _ptr(residual) if nr else None, _ptr(grad_out),
                            int(n_checkpoints), int(hbm_budget_bytes), _stream(stream)))
+
+
+def wf_born(model, dt: float, nt: int, src_xyz, src_wav, dm, rec_xyz, drec_out, rec_out=None,
+            stream=None):
+    ns, sp, _sa = _host(src_xyz)
+    nr, rp, _ra = _host(rec_xyz)
+    _check(lib.wf_born(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None, _ptr(dm),
+                       nr, rp, _ptr(drec_out) if nr else None,
+                       _ptr(rec_out) if (rec_out is not None and nr) else None, _stream(stream)))
 
 
 def wf_fwi_gradient(model, dt: float, nt: int, shots, grad_out, n_checkpoints: int = 0,

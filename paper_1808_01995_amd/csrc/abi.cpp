@@ -180,6 +180,25 @@ wf_status wf_gradient(wf_model* model, double dt, int nt, int nsrc, const double
     ABI_GUARD_END
 }
 
+wf_status wf_born(wf_model* model, double dt, int nt, int nsrc, const double* src_xyz,
+                  const float* src_wav, const float* dm, int nrec, const double* rec_xyz,
+                  float* drec_out, float* rec_out, void* stream) {
+    ABI_GUARD_BEGIN
+    if (!model) return fail(WF_E_ARG, "model is NULL");
+    Model& md = *as_model(model);
+    if (nt < 1) return fail(WF_E_ARG, "nt must be >= 1");
+    if (!dm) return fail(WF_E_ARG, "dm is NULL");
+    wf_status st;
+    if ((st = md.check_dt(dt)) != WF_OK) return st;
+    if ((st = check_series(nt, nsrc, src_wav, "src_wav")) != WF_OK) return st;
+    if ((st = check_series(nt, nrec, drec_out, "drec_out")) != WF_OK) return st;
+    const PointSet *src = nullptr, *rec = nullptr;
+    if ((st = md.points(nsrc, src_xyz, &src)) != WF_OK) return st;
+    if ((st = md.points(nrec, rec_xyz, &rec)) != WF_OK) return st;
+    return run_born(md, dt, nt, *src, src_wav, dm, *rec, drec_out, rec_out, as_stream(stream));
+    ABI_GUARD_END
+}
+
 wf_status wf_fwi_gradient(wf_model* model, double dt, int nt, int nshots, const wf_shot* shots,
                           float* grad_out, double* misfit_out, int n_checkpoints,
                           int64_t hbm_budget_bytes, void* stream) {

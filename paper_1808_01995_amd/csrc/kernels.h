@@ -14,6 +14,15 @@ constexpr int kMaxHalf = 8;   // space order up to 16
 // step kernel reads (it needs M + prefetch distance <= 10 of them).
 constexpr int kGhostPlanes = 12;
 
+// What the step kernel does besides the update (template variants).
+enum StepMode : int {
+    kModePlain = 0,         // the update only
+    kModeImaging = 1,       // grad -= ufwd (out - 2 cur + old) / dt^2   (adjoint sweep of the gradient)
+    kModeBornSource = 2,    // grad = -ufwd (out - 2 cur + old), ufwd = dm   (Born source of the next scattered step)
+    kModeVolumeSource = 3,  // kap vsrc / dt^2 added inside the update   (a source on every node)
+    kModeCount = 4
+};
+
 // Parameters of one time step of the fused update
 //   out = (2 cur - (1 - g) old + kap * Lap(cur)) / (1 + g),  g = eta kap / (2 dt)
 // on a pitched field layout: element (x, y, z) at x*sx + y*sy + z, sy = pitch
@@ -23,7 +32,10 @@ constexpr int kGhostPlanes = 12;
 // `out` may alias `old` (in-place update; every element of old is read by the
 // thread that then writes the same element of out).
 // With imaging on (adjoint sweeps of the gradient): grad -= ufwd * (out - 2 cur
-// + old) / dt^2, using `out` before any receiver injection.
+// + old) / dt^2, using `out` before any receiver injection (whose part the
+// injecting thread subtracts itself). Born source: grad = -ufwd * (out - 2 cur +
+// old) with out after injection. Volume source: the numerator of the update
+// gets kap * vsrc / dt^2, i.e. out += (dt^2 / a) * vsrc / dt^2 * dt^2.
 struct StepParams {
     const float* cur;
     const float* old;
@@ -34,6 +46,7 @@ struct StepParams {
     const float* etaz;
     float* grad;
     const float* ufwd;
+    const float* vsrc;   // volume source (kModeVolumeSource), pitched like the fields
     int nx, ny, nz;      // ny == 1 in 2D
     int64_t sx, sy;      // strides in floats
     int cx;              // x-chunk length per block
@@ -92,10 +105,10 @@ struct TileShape {
 TileShape step_tile(int ndim, int tile);
 // Choose the tile shape and the x-chunking (ntz/nty/nchunks/nblocks/cx); a
 // positive cx_request forces the chunk length, tile_request >= 0 the shape.
-void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request);
+void step_plan(StepParams& p, int ndim, int half, int mode, int cx_request, int tile_request);
 // Threads per block of the step kernel for a dimension and tile shape.
 int step_threads(int ndim, int tile);
-hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s);
+hipError_t launch_step(const StepParams& p, int ndim, int half, int mode, hipStream_t s);
 
 // Sparse injection at unique nodes (deterministic, no atomics):
 //   field[off[i]] += scale_i * sum_{e in seg i} w[e] * vals[pt[e]],
@@ -112,6 +125,7 @@ struct InjectParams {
     const float* vals;   // one row of the [nt][npts] series
     float* grad;
     const float* ufwd;
+    const float* vsrc;   // volume source (kModeVolumeSource), pitched like the fields
     int nnodes;
     float inv2dt, idt2;
 };

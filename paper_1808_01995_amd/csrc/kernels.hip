@@ -96,8 +96,11 @@ __device__ __forceinline__ float update(float c, float old, float kap, float lap
 // only overwrite a buffer after every thread has passed the barrier of the
 // plane in between.
 // ---------------------------------------------------------------------------
-template <bool D3, int M, int BZ, int BY, int PF, bool IMG>
+template <bool D3, int M, int BZ, int BY, int PF, int MODE>
 __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
+    constexpr bool IMG = MODE == kModeImaging;
+    constexpr bool BSRC = MODE == kModeBornSource;
+    constexpr bool VSRC = MODE == kModeVolumeSource;
     constexpr int NT = BZ * BY;
     constexpr int TZ = 4 * BZ;
     constexpr int P = (M + 3) & ~3;     // z halo rounded up to whole float4s
@@ -214,6 +217,8 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
             uf_n = ld4s(p.ufwd + b + col);
             gr_n = ld4s(p.grad + b + col);
         }
+        if (BSRC) uf_n = ld4s(p.ufwd + b + col);
+        if (VSRC) uf_n = ld4s(p.vsrc + b + col);
 #pragma unroll
         for (int j = 0; j < JY; ++j) hy_n[j] = ld4(p.cur + b + hy_c[j]);
 #pragma unroll
@@ -305,6 +310,10 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
                             lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
                 }
 
+                if (VSRC) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) lap[i] = fmaf(comp(uf, i), p.idt2, lap[i]);
+                }
                 float4 o;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -318,6 +327,13 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
                     for (int i = 0; i < 4; ++i) {
                         const float lapt = comp(o, i) - 2.0f * comp(c, i) + comp(uo, i);
                         set_comp(g2, i, comp(gr, i) - comp(uf, i) * lapt * p.idt2);
+                    }
+                }
+                if (BSRC) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float lapt = comp(o, i) - 2.0f * comp(c, i) + comp(uo, i);
+                        set_comp(g2, i, -comp(uf, i) * lapt);
                     }
                 }
                 // sources owned by this thread at this plane (rare, divergent)
@@ -338,21 +354,27 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
                         g2.z -= uf.z * i2 * p.idt2;
                         g2.w -= uf.w * i3 * p.idt2;
                     }
+                    if (BSRC) {
+                        g2.x -= uf.x * i0;
+                        g2.y -= uf.y * i1;
+                        g2.z -= uf.z * i2;
+                        g2.w -= uf.w * i3;
+                    }
                     ++inj_i;
                 }
                 if (own) {
                     const int64_t base = (int64_t)x * sx;
                     st4s(p.out + base + col, o);
-                    if (IMG) st4s(p.grad + base + col, g2);
+                    if (IMG || BSRC) st4s(p.grad + base + col, g2);
                 }
             }
         }
     }
 }
 
-template <bool D3, int M, int BZ, int BY, int PF, bool IMG>
+template <bool D3, int M, int BZ, int BY, int PF, int MODE>
 __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
-    step_body<D3, M, BZ, BY, PF, IMG>(p, (int)blockIdx.x);
+    step_body<D3, M, BZ, BY, PF, MODE>(p, (int)blockIdx.x);
 }
 
 // Many grids of one dimension and order advanced by one step in one launch
@@ -386,7 +408,7 @@ __global__ void __launch_bounds__(BZ * BY) k_step_batch(const BatchJob* __restri
     }
     if (p.inj_blk) p.inj_inc += n * J.inj_stride;
     if (p.smp_out) p.smp_out += n * J.smp_stride;
-    step_body<D3, M, BZ, BY, PF, false>(p, b - J.block_begin);
+    step_body<D3, M, BZ, BY, PF, kModePlain>(p, b - J.block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -557,44 +579,54 @@ int grid_1d(int64_t n, int block) {
 constexpr TileShape kTiles3[2] = {{32, 8}, {16, 16}};
 constexpr TileShape kTile2 = {64, 1};
 
-template <int M, int T, bool IMG>
+template <int M, int T, int MODE>
 const void* step3_fn() {
     constexpr int PF = M <= 4 ? WF_PF_LO : WF_PF_HI;
-    return reinterpret_cast<const void*>(&k_step<true, M, kTiles3[T].bz, kTiles3[T].by, PF, IMG>);
+    return reinterpret_cast<const void*>(&k_step<true, M, kTiles3[T].bz, kTiles3[T].by, PF, MODE>);
 }
-template <int M, bool IMG>
+template <int M, int MODE>
 const void* step2_fn() {
     constexpr int PF = M <= 4 ? WF_PF_LO : WF_PF_HI;
-    return reinterpret_cast<const void*>(&k_step<false, M, kTile2.bz, kTile2.by, PF, IMG>);
+    return reinterpret_cast<const void*>(&k_step<false, M, kTile2.bz, kTile2.by, PF, MODE>);
+}
+
+template <int M, int MODE>
+const void* step_fn_mm(int ndim, int tile) {
+    if (ndim == 2) return step2_fn<M, MODE>();
+    if (tile == 0) return step3_fn<M, 0, MODE>();
+    return step3_fn<M, 1, MODE>();
 }
 
 template <int M>
-const void* step_fn_m(int ndim, int tile, bool img) {
-    if (ndim == 2) return img ? step2_fn<M, true>() : step2_fn<M, false>();
-    if (tile == 0) return img ? step3_fn<M, 0, true>() : step3_fn<M, 0, false>();
-    return img ? step3_fn<M, 1, true>() : step3_fn<M, 1, false>();
-}
-
-const void* step_fn(int ndim, int half, int tile, bool img) {
-    switch (half) {
-        case 2: return step_fn_m<2>(ndim, tile, img);
-        case 3: return step_fn_m<3>(ndim, tile, img);
-        case 4: return step_fn_m<4>(ndim, tile, img);
-        case 5: return step_fn_m<5>(ndim, tile, img);
-        case 6: return step_fn_m<6>(ndim, tile, img);
-        case 7: return step_fn_m<7>(ndim, tile, img);
-        case 8: return step_fn_m<8>(ndim, tile, img);
+const void* step_fn_m(int ndim, int tile, int mode) {
+    switch (mode) {
+        case kModePlain: return step_fn_mm<M, kModePlain>(ndim, tile);
+        case kModeImaging: return step_fn_mm<M, kModeImaging>(ndim, tile);
+        case kModeBornSource: return step_fn_mm<M, kModeBornSource>(ndim, tile);
+        case kModeVolumeSource: return step_fn_mm<M, kModeVolumeSource>(ndim, tile);
         default: return nullptr;
     }
 }
 
-// Resident blocks of a step kernel on the whole device (cached).
-int step_capacity(int ndim, int half, int tile, bool img) {
+const void* step_fn(int ndim, int half, int tile, int mode) {
+    switch (half) {
+        case 2: return step_fn_m<2>(ndim, tile, mode);
+        case 3: return step_fn_m<3>(ndim, tile, mode);
+        case 4: return step_fn_m<4>(ndim, tile, mode);
+        case 5: return step_fn_m<5>(ndim, tile, mode);
+        case 6: return step_fn_m<6>(ndim, tile, mode);
+        case 7: return step_fn_m<7>(ndim, tile, mode);
+        case 8: return step_fn_m<8>(ndim, tile, mode);
+        default: return nullptr;
+    }
+}
+
+int step_capacity(int ndim, int half, int tile, int mode) {
     static std::mutex mu;
-    static int cache[2][kMaxHalf + 1][2][2] = {};
+    static int cache[2][kMaxHalf + 1][2][kModeCount] = {};
     static int cus = 0;
     std::lock_guard<std::mutex> lk(mu);
-    int& c = cache[ndim - 2][half][tile][img ? 1 : 0];
+    int& c = cache[ndim - 2][half][tile][mode];
     if (c > 0) return c;
     if (cus == 0) {
         int dev = 0;
@@ -604,7 +636,7 @@ int step_capacity(int ndim, int half, int tile, bool img) {
     }
     const TileShape ts = step_tile(ndim, tile);
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_fn(ndim, half, tile, img),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_fn(ndim, half, tile, mode),
                                                      ts.bz * ts.by, 0) != hipSuccess ||
         per < 1)
         per = 1;
@@ -631,7 +663,7 @@ TileShape step_tile(int ndim, int tile) {
     return kTile2;
 }
 
-void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, int tile_request) {
+void step_plan(StepParams& p, int ndim, int half, int mode, int cx_request, int tile_request) {
     int tile = 0;
     if (ndim == 3) {
         if (tile_request == 0 || tile_request == 1) {
@@ -651,7 +683,7 @@ void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, 
         // Chunks along x trade parallelism against the 2M + PF planes every
         // chunk re-reads to fill its register ring. Cost model per resident
         // round of blocks: (planes + warm-up) / occupancy, times the rounds.
-        const int cap = step_capacity(ndim, half, tile, imaging);
+        const int cap = step_capacity(ndim, half, tile, mode);
         const int warm = 2 * half + 1;
         double best = 1e300;
         int best_n = 1;
@@ -674,9 +706,9 @@ void step_plan(StepParams& p, int ndim, int half, bool imaging, int cx_request, 
     p.nblocks = (int)(tiles * p.nchunks);
 }
 
-hipError_t launch_step(const StepParams& p, int ndim, int half, bool imaging, hipStream_t s) {
+hipError_t launch_step(const StepParams& p, int ndim, int half, int mode, hipStream_t s) {
     if (p.nblocks <= 0) return hipSuccess;
-    const void* fn = step_fn(ndim, half, p.tile, imaging);
+    const void* fn = step_fn(ndim, half, p.tile, mode);
     if (!fn) return hipErrorInvalidValue;
     const TileShape ts = step_tile(ndim, p.tile);
     const int grid = ((p.nblocks + 7) / 8) * 8;

@@ -32,14 +32,14 @@ namespace {
     } while (0)
 
 wf_status step(StepParams& p, const Model& md, const float* cur, const float* old, float* out,
-               bool img, float* grad, const float* ufwd, hipStream_t s) {
+               int mode, float* grad, const float* ufwd, hipStream_t s) {
     p.cur = cur;
     p.old = old;
     p.out = out;
     p.grad = grad;
     p.ufwd = ufwd;
     ProfScope prof(WF_KERNEL_STEP, s);
-    return hip_check(launch_step(p, md.geom.ndim, md.half, img, s), "stencil launch");
+    return hip_check(launch_step(p, md.geom.ndim, md.half, mode, s), "stencil launch");
 }
 
 wf_status inject(const Model& md, const PointSet& ps, const float* vals, float* field, float* grad,
@@ -280,7 +280,7 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
             // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
             inj.configure(ps, n);
             set_sampling(ps, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr);
-            WF_TRY(step(ps, md, A, B, B, false, nullptr, nullptr, q));
+            WF_TRY(step(ps, md, A, B, B, kModePlain, nullptr, nullptr, q));
             WF_TRY(inj.after(md, n, B, nullptr, nullptr, ps, q));
             if (u_save && (n + 1) % save_every == 0)
                 WF_TRY(hip_check(launch_unpitch(B, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
@@ -318,7 +318,7 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
             // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
             inj.configure(ps, n + 1);
             set_sampling(ps, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr);
-            WF_TRY(step(ps, md, A, B, B, false, nullptr, nullptr, q));
+            WF_TRY(step(ps, md, A, B, B, kModePlain, nullptr, nullptr, q));
             WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, ps, q));
             std::swap(A, B);
         }
@@ -385,7 +385,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
     WF_TRY(md.ensure_kap(dt, s));
     StepParams p, pi;
     md.fill_step(p, dt);
-    md.fill_step(pi, dt, true);
+    md.fill_step(pi, dt, kModeImaging);
     const int64_t l = nt - 1;                     // adjoint steps n = 0..nt-2
     const int64_t nrec = rec.npts;
     if (l <= 0) {
@@ -444,7 +444,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
         } else {
             set_sampling(p, nullptr, nullptr);
         }
-        WF_TRY(step(p, md, cur, old, out, false, nullptr, nullptr, s));
+        WF_TRY(step(p, md, cur, old, out, kModePlain, nullptr, nullptr, s));
         return qinj.after(md, n, out, nullptr, nullptr, p, s);
     };
     // before the first reverse step: the last record row and the residual
@@ -464,7 +464,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
     auto reverse_step = [&](int64_t n, const float* u_np1) -> wf_status {
         WF_TRY(form_residual(u_np1));
         rinj.configure(pi, n + 1);
-        WF_TRY(step(pi, md, V1, V2, V2, true, G, u_np1, s));
+        WF_TRY(step(pi, md, V1, V2, V2, kModeImaging, G, u_np1, s));
         WF_TRY(rinj.after(md, n + 1, V2, G, u_np1, pi, s));
         std::swap(V1, V2);
         return WF_OK;
@@ -626,6 +626,63 @@ wf_status run_fwi_gradient(Model& md, double dt, int nt, const std::vector<FwiSh
 }
 
 // ---------------------------------------------------------------------------
+// linearised (Born) modelling
+// ---------------------------------------------------------------------------
+// Background step n (kModeBornSource) writes u^{n+1} over u^{n-1} and the
+// scattered source W = -dm (u^{n+1} - 2 u^n + u^{n-1}); the scattered step n
+// (kModeVolumeSource) then advances du with W / dt^2 weighted like a point
+// source (dt^2 / a). Receivers: d^n = P_r u^n and dd^n = P_r du^n, sampled
+// inside the two launches.
+wf_status run_born(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                   const float* dm, const PointSet& rec, float* drec_out, float* rec_out,
+                   hipStream_t s) {
+    const Layout& L = md.L;
+    const int64_t nrec = rec.npts;
+    WF_TRY(md.ensure_kap(dt, s));
+    FieldPool f;
+    WF_TRY(f.alloc(L, 4, s));   // zeroed: du^n, du^{n-1}, W, dm (pitched)
+    float* dA = f.at(0);
+    float* dB = f.at(1);
+    float* W = f.at(2);
+    float* DM = f.at(3);
+    WF_TRY(hip_check(launch_pitch(dm, DM, L.nx, L.ny, L.nz, L.sx, L.sy, s), "pitch dm"));
+    float* A = md.u(0);
+    float* B = md.u(1);
+    WF_TRY(hip_check(launch_fill(A, L.elems, 0.0f, s), "fill"));
+    WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, s), "fill"));
+    StepParams pu, pd;
+    md.fill_step(pu, dt, kModeBornSource);
+    md.fill_step(pd, dt, kModeVolumeSource);
+    pd.vsrc = W;
+    Injector inj;
+    WF_TRY(inj.prepare(md, src, pu, src_wav, nt, md.d_inc[0], s));
+    // the separate injection kernel subtracts ufwd * inc * idt2 from grad:
+    // with idt2 = 1 that is the Born source's share of the injected value
+    StepParams pw = pu;
+    pw.idt2 = 1.0f;
+    if (nt == 1 && nrec > 0) {
+        WF_TRY(hip_check(launch_fill(drec_out, nrec, 0.0f, s), "fill"));
+        if (rec_out) WF_TRY(hip_check(launch_fill(rec_out, nrec, 0.0f, s), "fill"));
+    }
+    for (int n = 0; n + 1 < nt; ++n) {
+        inj.configure(pu, n);
+        set_sampling(pu, &rec, (rec_out && nrec) ? rec_out + (int64_t)n * nrec : nullptr);
+        WF_TRY(step(pu, md, A, B, B, kModeBornSource, W, DM, s));
+        WF_TRY(inj.after(md, n, B, W, DM, pw, s));
+        set_sampling(pd, &rec, nrec ? drec_out + (int64_t)n * nrec : nullptr);
+        WF_TRY(step(pd, md, dA, dB, dB, kModeVolumeSource, nullptr, nullptr, s));
+        std::swap(A, B);
+        std::swap(dA, dB);
+    }
+    if (nt > 1) {
+        WF_TRY(sample(rec, dA, drec_out + (int64_t)(nt - 1) * nrec, s));
+        if (rec_out) WF_TRY(sample(rec, A, rec_out + (int64_t)(nt - 1) * nrec, s));
+    }
+    // the pool is freed when this returns
+    return hip_check(hipStreamSynchronize(s), "sync");
+}
+
+// ---------------------------------------------------------------------------
 // batched forward shots
 // ---------------------------------------------------------------------------
 wf_status batch_forward_begin(Model& md, double dt, int nt, const PointSet& src, const float* wav,
@@ -650,7 +707,7 @@ wf_status batch_forward_begin(Model& md, double dt, int nt, const PointSet& src,
     // stream of orders 4/8/12: 8 planes best in 2D, 16 in 3D)
     int cx = std::min(L.nx, md.geom.ndim == 2 ? 8 : 16);
     if (const char* e = std::getenv("WAVEFD_BATCH_CX")) cx = std::max(1, std::min(L.nx, std::atoi(e)));
-    step_plan(p, md.geom.ndim, md.half, false, cx, p.tile);
+    step_plan(p, md.geom.ndim, md.half, kModePlain, cx, p.tile);
     Injector inj;
     WF_TRY(inj.prepare(md, src, p, wav, nt, md.d_inc[0], s));
     if (src.nnodes > 0 && !inj.fz) return fail(WF_E_STATE, "sources cannot be injected by the batched kernel");

@@ -589,7 +589,7 @@ Model::~Model() {
     for (auto& c : pcache) delete c.ps;
 }
 
-void Model::fill_step(StepParams& p, double dt, bool imaging) const {
+void Model::fill_step(StepParams& p, double dt, int mode) const {
     std::memset(&p, 0, sizeof p);
     p.kap = kap();
     p.etax = d_etax.f();
@@ -616,5 +616,5 @@ void Model::fill_step(StepParams& p, double dt, bool imaging) const {
     int cx = 0, tile = -1;
     if (const char* s = std::getenv("WAVEFD_CX")) cx = std::atoi(s);
     if (const char* s = std::getenv("WAVEFD_TILE")) tile = std::atoi(s);
-    step_plan(p, geom.ndim, half, imaging, cx, tile);
+    step_plan(p, geom.ndim, half, mode, cx, tile);
 }

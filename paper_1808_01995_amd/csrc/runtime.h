@@ -161,7 +161,7 @@ struct Model : public wf_model {
     double vmax() const;
     wf_status points(int npts, const double* xyz, const wf::PointSet** out);
     // plan a step launch; sample_points > 0 leaves room for that many fused samples
-    void fill_step(wf::StepParams& p, double dt, bool imaging = false) const;
+    void fill_step(wf::StepParams& p, double dt, int mode = wf::kModePlain) const;
     float* u(int i) const { return L.field(d_u[i].ptr); }
     float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
@@ -198,6 +198,12 @@ wf_status run_gradient(Model& md, double dt, int nt, const PointSet& src, const 
                        const PointSet& rec, const float* residual, float* grad_out, int n_ck,
                        int64_t budget, hipStream_t s, const float* d_obs = nullptr,
                        float* d_pred_out = nullptr, double* misfit_out = nullptr);
+
+// Linearised modelling dd = J dm (dm dense); rec_out (optional) receives the
+// background record.
+wf_status run_born(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                   const float* dm, const PointSet& rec, float* drec_out, float* rec_out,
+                   hipStream_t s);
 
 // Observed-data terms of one gradient sweep (device buffers [nt][nrec]).
 struct ObsData {

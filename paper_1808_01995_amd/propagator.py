@@ -156,6 +156,21 @@ class Propagator:
         return g
 
 
+    def born(self, dt: float, nt: int, src_xyz, src_wav, dm: torch.Tensor, rec_xyz,
+             return_background: bool = False):
+        """Linearised modelling dd = J dm for a squared-slowness perturbation dm
+        on the computational grid; with return_background also P_r u."""
+        src_xyz = np.atleast_2d(np.asarray(src_xyz, dtype=np.float64))
+        rec_xyz = np.atleast_2d(np.asarray(rec_xyz, dtype=np.float64))
+        q = self._series(src_wav, nt, src_xyz.shape[0], "src_wav")
+        dm = dm.to(device=self.device, dtype=torch.float32).contiguous()
+        if tuple(dm.shape) != self.comp_shape:
+            raise ValueError("dm has shape %s, expected %s" % (tuple(dm.shape), self.comp_shape))
+        dd = torch.empty((nt, rec_xyz.shape[0]), dtype=torch.float32, device=self.device)
+        d = torch.empty_like(dd) if return_background else None
+        _abi.wf_born(self.handle, dt, nt, src_xyz, q, dm, rec_xyz, dd, d)
+        return (dd, d) if return_background else dd
+
     def fwi_gradient(self, dt: float, nt: int, shots, n_checkpoints: int = 0,
                      hbm_budget_bytes: int = 0, return_pred: bool = False):
         """Multi-shot FWI objective and gradient at the current m: shots is a
