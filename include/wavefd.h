@@ -172,10 +172,22 @@ wf_status wf_adjoint(wf_model* model, double dt, int nt,
  * [nt][nrec]); grad_out device FP32 Nc^D (dense, overwritten).
  *   n_checkpoints  > 0: revolve with that many stored states (2 fields each);
  *                  -1 : store every forward wavefield (no recomputation);
- *                   0 : the largest count that fits hbm_budget_bytes.
+ *                   0 : the largest count that fits hbm_budget_bytes;
+ *                  -2 : boundary-wavefield reconstruction (the alternative
+ *                       to checkpointing in Section "Discrete adjoint
+ *                       wave-equation and FWI gradient"): the forward sweep
+ *                       stores per step only the M-deep face slabs around
+ *                       the physical grid, and u is rebuilt backward on the
+ *                       physical grid during the adjoint sweep (one extra
+ *                       wave solve, memory 4 fields + nt x slabs). The
+ *                       damping layer cannot be rebuilt backward, so
+ *                       grad_out is the gradient on the physical grid and 0
+ *                       in the layer.
  *   hbm_budget_bytes  bound on the device memory the call may allocate for
  *                  checkpoints and its temporaries (0: no bound).
- * Results are bitwise identical for every checkpoint count. */
+ * Results are bitwise identical for every count >= -1; mode -2 agrees with
+ * them on the physical grid to FP32 rounding of the backward rebuild.
+ * The checkpoint pool is kept by the model for its next gradient call. */
 wf_status wf_gradient(wf_model* model, double dt, int nt,
                       int nsrc, const double* src_xyz, const float* src_wav,
                       int nrec, const double* rec_xyz, const float* residual,

@@ -166,7 +166,7 @@ wf_status wf_gradient(wf_model* model, double dt, int nt, int nsrc, const double
     Model& md = *as_model(model);
     if (nt < 1) return fail(WF_E_ARG, "nt must be >= 1");
     if (!grad_out) return fail(WF_E_ARG, "grad_out is NULL");
-    if (n_checkpoints < -1) return fail(WF_E_ARG, "n_checkpoints must be >= -1");
+    if (n_checkpoints < -2) return fail(WF_E_ARG, "n_checkpoints must be >= -2");
     if (hbm_budget_bytes < 0) return fail(WF_E_ARG, "negative budget");
     wf_status st;
     if ((st = md.check_dt(dt)) != WF_OK) return st;
@@ -208,7 +208,7 @@ wf_status wf_fwi_gradient(wf_model* model, double dt, int nt, int nshots, const 
     if (nt < 1) return fail(WF_E_ARG, "nt must be >= 1");
     if (nshots < 1 || !shots) return fail(WF_E_ARG, "at least one shot is needed");
     if (!grad_out) return fail(WF_E_ARG, "grad_out is NULL");
-    if (n_checkpoints < -1) return fail(WF_E_ARG, "n_checkpoints must be >= -1");
+    if (n_checkpoints < -2) return fail(WF_E_ARG, "n_checkpoints must be >= -2");
     if (hbm_budget_bytes < 0) return fail(WF_E_ARG, "negative budget");
     wf_status st;
     if ((st = md.check_dt(dt)) != WF_OK) return st;

@@ -169,6 +169,21 @@ hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count
 int residual_blocks(int64_t n);
 hipError_t launch_residual(const float* d, const float* d_obs, float* r, int64_t n, double* partial,
                            hipStream_t s);
+// Face slabs just outside an interior box: along each axis a slab M nodes
+// deep on either side, spanning the box along the other axes (clipped to the
+// grid). Their union holds every node outside the box that the order-2M
+// stencil of a box node reads.
+struct StripGeom {
+    int nslab = 0;
+    int64_t start[7] = {0, 0, 0, 0, 0, 0, 0};   // prefix counts of the slabs
+    int x0[6], x1[6], y0[6], y1[6], z0[6], z1[6];
+    int64_t sx = 0, sy = 0;
+};
+// to_field = 0: strip[i] = field[node i]; 1: field[node i] = strip[i]
+hipError_t launch_strip(float* field, float* strip, const StripGeom& g, int to_field, hipStream_t s);
+// zero every node of a pitched field outside [bx0,bx1) x [by0,by1) x [bz0,bz1)
+hipError_t launch_mask_box(float* field, int nx, int ny, int nz, int64_t sx, int64_t sy, int bx0,
+                           int bx1, int by0, int by1, int bz0, int bz1, hipStream_t s);
 // m[i] = min(max(m[i] - alpha g[i], lo), hi) (one rounding: fma)
 hipError_t launch_update(float* m, const float* g, float alpha, float lo, float hi, int64_t n,
                          hipStream_t s);

@@ -50,6 +50,19 @@ __device__ __forceinline__ float4 ld4s(const float* p) {
     return *reinterpret_cast<const float4*>(p);
 #endif
 }
+// The output store separately: WF_NT_OUT = 0 keeps the new field cacheable.
+#ifndef WF_NT_OUT
+#define WF_NT_OUT WF_STREAM_NT
+#endif
+__device__ __forceinline__ void st4o(float* p, const float4& v) {
+#if WF_NT_OUT
+    f4v t;
+    t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+    __builtin_nontemporal_store(t, reinterpret_cast<f4v*>(p));
+#else
+    *reinterpret_cast<float4*>(p) = v;
+#endif
+}
 __device__ __forceinline__ void st4s(float* p, const float4& v) {
 #if WF_STREAM_NT
     f4v t;
@@ -364,7 +377,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
                 }
                 if (own) {
                     const int64_t base = (int64_t)x * sx;
-                    st4s(p.out + base + col, o);
+                    st4o(p.out + base + col, o);
                     if (IMG || BSRC) st4s(p.grad + base + col, g2);
                 }
             }
@@ -547,6 +560,39 @@ __global__ void k_minmax(const float* __restrict__ x, int64_t n, unsigned int* o
     atomicMin(&out3[0], lo);
     atomicMax(&out3[1], hi);
     if (bad) atomicAdd(&out3[2], bad);
+}
+
+__global__ void k_strip(float* __restrict__ field, float* __restrict__ strip, const StripGeom g,
+                        int to_field) {
+    const int64_t n = g.start[g.nslab];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int k = 0;
+        while (k + 1 < g.nslab && i >= g.start[k + 1]) ++k;
+        const int64_t j = i - g.start[k];
+        const int64_t ez = g.z1[k] - g.z0[k], ey = g.y1[k] - g.y0[k];
+        const int64_t z = g.z0[k] + j % ez;
+        const int64_t t = j / ez;
+        const int64_t y = g.y0[k] + t % ey;
+        const int64_t x = g.x0[k] + t / ey;
+        const int64_t o = x * g.sx + y * g.sy + z;
+        if (to_field) field[o] = strip[i];
+        else strip[i] = field[o];
+    }
+}
+
+__global__ void k_mask_box(float* __restrict__ f, int nx, int ny, int nz, int64_t sx, int64_t sy,
+                           int bx0, int bx1, int by0, int by1, int bz0, int bz1) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(i % nz);
+        const int64_t t = i / nz;
+        const int y = (int)(t % ny);
+        const int x = (int)(t / ny);
+        if (x < bx0 || x >= bx1 || y < by0 || y >= by1 || z < bz0 || z >= bz1)
+            f[(int64_t)x * sx + (int64_t)y * sy + z] = 0.0f;
+    }
 }
 
 __global__ void k_update(float* __restrict__ m, const float* __restrict__ g, float alpha, float lo,
@@ -813,6 +859,22 @@ hipError_t launch_residual(const float* d, const float* d_obs, float* r, int64_t
 hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_1d(n, 256)), dim3(256), 0, s, x, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_strip(float* field, float* strip, const StripGeom& g, int to_field, hipStream_t s) {
+    const int64_t n = g.start[g.nslab];
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_strip, dim3(grid_1d(n, 256)), dim3(256), 0, s, field, strip, g, to_field);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_box(float* field, int nx, int ny, int nz, int64_t sx, int64_t sy, int bx0,
+                           int bx1, int by0, int by1, int bz0, int bz1, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mask_box, dim3(grid_1d(n, 256)), dim3(256), 0, s, field, nx, ny, nz, sx, sy,
+                       bx0, bx1, by0, by1, bz0, bz1);
     return hipGetLastError();
 }
 

@@ -364,11 +364,90 @@ struct FieldPool {
     }
     wf_status alloc(const Layout& L, int n, hipStream_t s) { return carve(own, L, n, s); }
     float* at(int i) const { return base + (int64_t)i * stride + off; }
+    float* raw(int i) const { return base + (int64_t)i * stride; }   // start of buffer i
 };
 
 }  // namespace
 
 namespace {
+
+// Boundary-wavefield reconstruction (Section "Discrete adjoint wave-equation
+// and FWI gradient", the alternative to checkpointing it describes): the
+// forward sweep stores, per step, only the face slabs around the physical grid
+// that its stencil reads; the reverse sweep rebuilds u backward on the physical
+// grid next to the adjoint field, with the same update (where eta = 0 it is
+// its own time reverse: u^{n-1} = 2 u^n - u^{n+1} + kappa L u^n + the injected
+// q^n) and the stored slabs restored after every step. One extra wave solve,
+// memory O(surface x nt). The layer itself is not rebuilt (reversing the
+// damping is unstable), so the gradient is formed on the physical grid and is
+// zero in the layer.
+wf_status gradient_boundary(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                            const PointSet& rec, const float* residual, const ObsData* obs, float* G,
+                            int64_t held, int64_t budget, hipStream_t s, StepParams& p,
+                            StepParams& pi) {
+    const Layout& L = md.L;
+    const int64_t fb = ((L.alloc_elems + 63) / 64 * 64) * 4;
+    const int64_t l = nt - 1;
+    const int64_t nrec = rec.npts;
+    const StripGeom sg = md.strips();
+    const int64_t per = sg.start[sg.nslab];                 // floats per stored step
+    const int64_t strip_fields = ((int64_t)nt * per * 4 + fb - 1) / fb;
+    int64_t cap = device_free_bytes() + held + md.ws.bytes;
+    if (budget > 0) cap = std::min<int64_t>(cap, budget);
+    const int64_t need = held + (4 + strip_fields) * fb;
+    if (need > cap) return fail(WF_E_BUDGET, "gradient needs %lld bytes, %lld available", (long long)need, (long long)cap);
+    FieldPool pool;
+    WF_TRY(pool.carve(md.ws, L, (int)(4 + strip_fields), s));
+    float* A = pool.at(0);    // u^n in the forward sweep, u^{n+1} in the reverse sweep
+    float* B = pool.at(1);
+    float* V1 = pool.at(2);   // v^{n+1}
+    float* V2 = pool.at(3);   // v^{n+2}, overwritten by v^n
+    float* strips = pool.raw(4);   // row n: the slabs of u^n (row 0 stays zero)
+
+    Injector qinj, rinj;
+    WF_TRY(qinj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
+    if (!obs) WF_TRY(rinj.prepare(md, rec, pi, residual, nt, md.d_inc[1], s));
+
+    // forward sweep: u^{n+1} over u^{n-1}, then its slabs into row n+1
+    for (int64_t n = 0; n < l; ++n) {
+        qinj.configure(p, n);
+        set_sampling(p, obs ? &rec : nullptr, (obs && nrec) ? obs->d_pred + n * nrec : nullptr);
+        WF_TRY(step(p, md, A, B, B, kModePlain, nullptr, nullptr, s));
+        WF_TRY(qinj.after(md, n, B, nullptr, nullptr, p, s));
+        WF_TRY(hip_check(launch_strip(B, strips + (n + 1) * per, sg, 0, s), "save strips"));
+        std::swap(A, B);
+    }
+    // now A = u^{nt-1}, B = u^{nt-2}
+    if (obs) {
+        if (nrec > 0) {
+            WF_TRY(sample(rec, A, obs->d_pred + l * nrec, s));
+            WF_TRY(hip_check(launch_residual(obs->d_pred, obs->d_obs, obs->resid, (int64_t)nt * nrec,
+                                             obs->partial, s), "residual"));
+        }
+        WF_TRY(rinj.prepare(md, rec, pi, obs->resid, nt, md.d_inc[1], s));
+    }
+    set_sampling(p, nullptr, nullptr);
+    for (int64_t n = l - 1; n >= 0; --n) {
+        // adjoint step n with imaging of term j = n+1 (A = u^{n+1})
+        rinj.configure(pi, n + 1);
+        WF_TRY(step(pi, md, V1, V2, V2, kModeImaging, G, A, s));
+        WF_TRY(rinj.after(md, n + 1, V2, G, A, pi, s));
+        std::swap(V1, V2);
+        if (n >= 2) {
+            // u^{n-1} = 2 u^n - u^{n+1} + kappa L u^n + q^n's injection, over u^{n+1}
+            qinj.configure(p, n);
+            WF_TRY(step(p, md, B, A, A, kModePlain, nullptr, nullptr, s));
+            WF_TRY(qinj.after(md, n, A, nullptr, nullptr, p, s));
+            WF_TRY(hip_check(launch_strip(A, strips + (n - 1) * per, sg, 1, s), "restore strips"));
+        }
+        std::swap(A, B);   // A = u^n for the next adjoint step
+    }
+    int b0[3], b1[3];
+    md.interior(b0, b1);
+    WF_TRY(hip_check(launch_mask_box(G, L.nx, L.ny, L.nz, L.sx, L.sy, b0[0], b1[0], b0[1], b1[1], b0[2],
+                                     b1[2], s), "mask"));
+    return hip_check(hipStreamSynchronize(s), "sync");
+}
 
 // One shot's adjoint-state gradient added into the pitched accumulator G.
 // With `obs`, the residual is formed inside the call: the first forward sweep
@@ -397,6 +476,8 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
         }
         return WF_OK;
     }
+    if (n_ck == -2)
+        return gradient_boundary(md, dt, nt, src, src_wav, rec, residual, obs, G, held, budget, s, p, pi);
     // memory plan: adjoint pair + what the caller holds (accumulator, record
     // scratch) plus either every forward field (store-all: nt fields incl. one
     // zero field) or a revolve pool of 2 s + 3 fields
@@ -415,7 +496,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
             if (snaps < 1) return fail(WF_E_BUDGET, "gradient needs at least %lld bytes", (long long)(fixed + 5 * fb));
         }
     } else if (n_ck < -1) {
-        return fail(WF_E_ARG, "n_checkpoints must be >= -1");
+        return fail(WF_E_ARG, "n_checkpoints must be >= -2");
     }
     if (!store_all) snaps = (int)std::min<int64_t>(snaps, l);
     const int nbuf = store_all ? nt : 2 * snaps + 3;

@@ -504,6 +504,50 @@ wf_status Model::update(const float* grad, double alpha, double lo, double hi, f
     return refresh_m(s);
 }
 
+void Model::interior(int b0[3], int b1[3]) const {
+    const int nb = geom.nbl;
+    b0[0] = nb;
+    b1[0] = nb + (int)geom.n[0];
+    if (geom.ndim == 3) {
+        b0[1] = nb;
+        b1[1] = nb + (int)geom.n[1];
+    } else {
+        b0[1] = 0;
+        b1[1] = 1;
+    }
+    b0[2] = nb;
+    b1[2] = nb + (int)geom.n[geom.ndim - 1];
+}
+
+StripGeom Model::strips() const {
+    StripGeom g;
+    g.sx = L.sx;
+    g.sy = L.sy;
+    int b0[3], b1[3];
+    interior(b0, b1);
+    const int N[3] = {L.nx, L.ny, L.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (a == 1 && geom.ndim == 2) continue;
+        for (int side = 0; side < 2; ++side) {
+            int lo[3] = {b0[0], b0[1], b0[2]}, hi[3] = {b1[0], b1[1], b1[2]};
+            if (side == 0) {
+                lo[a] = std::max(0, b0[a] - half);
+                hi[a] = b0[a];
+            } else {
+                lo[a] = b1[a];
+                hi[a] = std::min(N[a], b1[a] + half);
+            }
+            if (hi[a] <= lo[a]) continue;
+            const int k = g.nslab++;
+            g.x0[k] = lo[0]; g.x1[k] = hi[0];
+            g.y0[k] = lo[1]; g.y1[k] = hi[1];
+            g.z0[k] = lo[2]; g.z1[k] = hi[2];
+            g.start[k + 1] = g.start[k] + (int64_t)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+        }
+    }
+    return g;
+}
+
 double Model::vmax() const { return 1.0 / std::sqrt(m_min); }
 
 wf_status Model::ensure_kap(double dt, hipStream_t s) {

@@ -154,6 +154,10 @@ struct Model : public wf_model {
     wf_status init(const wf_geom* g, const float* m_dev, hipStream_t s);
     wf_status set_m(const float* m_dev, hipStream_t s);
     wf_status refresh_m(hipStream_t s);
+    // the physical grid as a box [b0, b1) per layout axis (x, y, z; y = [0, 1) in 2D)
+    void interior(int b0[3], int b1[3]) const;
+    // the face slabs around that box that its stencil reads (boundary strips)
+    wf::StripGeom strips() const;
     // m <- min(max(m - alpha grad, lo), hi); m_out (optional) receives it
     wf_status update(const float* grad, double alpha, double lo, double hi, float* m_out, hipStream_t s);
     wf_status ensure_kap(double dt, hipStream_t s);

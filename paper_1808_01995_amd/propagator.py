@@ -145,7 +145,10 @@ class Propagator:
 
     def gradient(self, dt: float, nt: int, src_xyz, src_wav, rec_xyz, residual,
                  n_checkpoints: int = 0, hbm_budget_bytes: int = 0):
-        """J^T r on the computational grid for the residual r = P_r u - d_obs."""
+        """J^T r on the computational grid for the residual r = P_r u - d_obs.
+        n_checkpoints: s > 0 revolve states, -1 store all, 0 as many as the
+        budget allows, -2 boundary-wavefield reconstruction (the gradient on
+        the physical grid, 0 in the layer)."""
         src_xyz = np.atleast_2d(np.asarray(src_xyz, dtype=np.float64))
         rec_xyz = np.atleast_2d(np.asarray(rec_xyz, dtype=np.float64))
         q = self._series(src_wav, nt, src_xyz.shape[0], "src_wav")

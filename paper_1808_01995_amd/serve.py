@@ -55,7 +55,7 @@ class Request:
         n = 1
         for a in range(self.geom.ndim):
             n *= self.geom.n[a] + 2 * self.geom.nbl
-        return n * (self.nt - 1) * (3 if self.kind == _abi.WF_REQ_GRADIENT else 1)
+        return n * (self.nt - 1) * (2 if self.kind == _abi.WF_REQ_GRADIENT else 1)   # a gradient is two solves
 
 
 def build_request(spec: Dict, device="cuda", vmin: float = 1.5, vmax: float = 4.5,
@@ -194,7 +194,9 @@ def run_stream(server: Server, requests: List[Request], arrivals: Optional[List[
 
 def run_one_shot_baseline(requests: List[Request]) -> Dict:
     """The plain propagator, one request at a time (model created per request,
-    one kernel launch per time step): the reference throughput mu_0."""
+    one kernel launch per time step; gradients by the two-solve multi-shot
+    call with one shot, the same work the engine does): the reference
+    throughput mu_0."""
     t0 = time.perf_counter()
     outs = []
     for r in requests:
@@ -202,11 +204,12 @@ def run_one_shot_baseline(requests: List[Request]) -> Dict:
         shape = tuple(r.geom.n[a] for a in range(nd))
         prop = Propagator(m=r.m, shape=shape, spacing=tuple(r.geom.h[a] for a in range(nd)),
                           nbl=r.geom.nbl, space_order=r.geom.space_order, c_ref=r.geom.c_ref)
-        d = prop.forward(r.dt, r.nt, r.src_xyz, r.src_wav, r.rec_xyz)
         if r.kind == _abi.WF_REQ_GRADIENT:
-            g = prop.gradient(r.dt, r.nt, r.src_xyz, r.src_wav, r.rec_xyz, (d - r.d_obs).contiguous())
+            _, g, (d,) = prop.fwi_gradient(r.dt, r.nt, [(r.src_xyz, r.src_wav, r.rec_xyz, r.d_obs)],
+                                           return_pred=True)
             outs.append((d, g))
         else:
+            d = prop.forward(r.dt, r.nt, r.src_xyz, r.src_wav, r.rec_xyz)
             outs.append((d, None))
         torch.cuda.synchronize()
         prop.close()

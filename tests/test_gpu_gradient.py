@@ -149,3 +149,37 @@ def test_gradient_workspace_kept_and_trimmed():
     assert _abi.wf_model_bytes(prop.handle) < b1
     g3 = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
     assert torch.equal(g1, g2) and torch.equal(g1, g3)
+
+
+@pytest.mark.parametrize("ndim,nbl", [(2, 8), (3, 6), (2, 0)])
+def test_boundary_reconstruction_gradient(ndim, nbl):
+    """n_checkpoints = -2: u rebuilt backward from stored boundary slabs.
+    On the physical grid it matches the oracle gradient (<= 1e-3) and the
+    store-all GPU gradient to FP32 rounding of the rebuild; the layer is 0;
+    the workspace is 4 fields plus the slabs."""
+    from paper_1808_01995_amd import _abi
+    n = 36 if ndim == 3 else 90
+    P, Pt = _anomaly_problem(ndim=ndim, n=n, nbl=nbl, steps=150 if ndim == 3 else 300)
+    d_obs = Pt.oracle_forward()
+    d0 = P.oracle_forward()
+    res32 = (d0 - d_obs).astype(np.float32)
+    g_ref = P.oracle_gradient(res32.astype(np.float64))
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    r = torch.from_numpy(res32).cuda()
+    g_all = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1).cpu().numpy()
+    prop.trim()
+    base = _abi.wf_model_bytes(prop.handle)
+    g_b = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-2).cpu().numpy()
+    ws = _abi.wf_model_bytes(prop.handle) - base
+    inner = tuple(slice(nbl, nbl + n) for _ in range(ndim))
+    mask = np.ones(g_b.shape, dtype=bool)
+    mask[inner] = False
+    assert np.all(g_b[mask] == 0)
+    e_all = rel_l2(g_b[inner], g_all[inner])
+    e_ref = rel_l2(g_b[inner], g_ref[inner])
+    print("boundary rebuild %dD nbl %d: vs store-all %.2e, vs oracle %.2e, workspace %.1f fields"
+          % (ndim, nbl, e_all, e_ref, ws / (prop.npoints * 4)))
+    assert e_all <= 1e-4
+    assert e_ref <= 1e-3
+    assert ws < (P.nt // 2) * prop.npoints * 4
