@@ -52,6 +52,21 @@ def test_gradient_parity_with_oracle(ndim):
     assert err <= 1e-3
 
 
+def test_gradient_parity_wide_z_tile():
+    """Imaging kernel with a half-empty last z tile (z length 190),
+    band-limited residual."""
+    from _harness import noise
+    P = make_problem((28, 20, 174), 8, 8, 70, seed=77, nrec=30)
+    res32 = noise(P.nt, P.rec_xyz.shape[0], P.dt, 15.0, 5).astype(np.float32)
+    g_ref = P.oracle_gradient(res32.astype(np.float64))
+    prop = P.propagator()
+    g = prop.gradient(P.dt, P.nt, P.src_xyz, torch.from_numpy(P.q32).cuda(), P.rec_xyz,
+                      torch.from_numpy(res32).cuda(), n_checkpoints=-1).cpu().numpy()
+    err = rel_l2(g, g_ref)
+    print("gradient (z length 190) rel L2 = %.3g" % err)
+    assert err <= 1e-3
+
+
 def test_gradient_bitwise_across_checkpoint_counts():
     P, Pt = _anomaly_problem(n=30, steps=97)
     d_obs = Pt.oracle_forward()

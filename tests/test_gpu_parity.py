@@ -63,6 +63,17 @@ def test_3d_orders_ragged_tiles(k):
     assert err <= 1e-4
 
 
+@pytest.mark.parametrize("k,nz_phys", [(8, 174), (16, 174), (4, 260)])
+def test_3d_wide_tiles(k, nz_phys):
+    """Wider z lengths on the 128 x 8 tile: 190 nodes (last z tile half
+    empty) and 276 nodes, with ragged y tiles and x chunks."""
+    P = make_problem((30, 21, nz_phys), 8, k, 60, seed=70 + k, nrec=40)
+    d = _gpu_forward(P).cpu().numpy()
+    err = rel_l2(d, P.oracle_forward())
+    print("3D k=%d nz=%d rel L2 = %.3g" % (k, nz_phys + 16, err))
+    assert err <= 1e-4
+
+
 def test_3d_so8_two_layer_and_save():
     P = make_problem((40, 36, 44), 10, 8, 80, seed=3, kind="two_layer", nrec=50)
     d, u = _gpu_forward(P, save_every=20)
