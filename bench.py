@@ -336,6 +336,28 @@ def serving_c5(torch, n_requests=48, scale_down=2, max_steps=1000, seed=5):
             "max_rel_l2_vs_one_shot": rel}
 
 
+def profile_kernels(torch, steps=400):
+    """A short run of every step-kernel mode for rocprofv3: 280^3 order 8,
+    v = 2 km/s, 100 x 100 receivers; two store-all gradients (plain and
+    imaging modes) for a random residual and two Born modellings (Born-source
+    and volume-source modes) for a random perturbation."""
+    from paper_1808_01995_amd import Propagator
+    from synthetic import config, ricker
+    c = config("c4_gradient", steps=steps)
+    p0 = Propagator(np.full(c.shape, 2.0), spacing=c.spacing, nbl=c.nbl, space_order=8, c_ref=2.5)
+    dt = 0.5 * p0.critical_dt(2.5)
+    q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    r = torch.randn((c.nt, c.rec.shape[0]), device="cuda", generator=gen)
+    dm = torch.randn(p0.comp_shape, device="cuda", generator=gen) * 1e-3
+    for _ in range(2):
+        p0.gradient(dt, c.nt, c.src, q, c.rec, r, n_checkpoints=-1)
+        p0.born(dt, c.nt, c.src, q, dm, c.rec)
+    torch.cuda.synchronize()
+    p0.close()
+    print(json.dumps({"profile_kernels": "done", "grid": list(p0.comp_shape), "updates": steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +373,9 @@ def main():
                     help="shorter shots (profiling runs only; the benchmark uses 1000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run the gradient and Born kernels for a profiler: 280^3 order 8, "
+                         "400 updates, two store-all gradients and two Born modellings")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -371,6 +396,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_launch": a.numel() * 4}), flush=True)
         return
     from paper_1808_01995_amd import _abi
+    if args.profile_kernels:
+        profile_kernels(torch)
+        return
 
     c, v, prop, dt, q, rec_out = setup_c2(torch, args.space_order, args.updates)
     npts = prop.npoints

@@ -100,6 +100,7 @@ wf_status wf_model_trim(wf_model* model) {
     wf_status st = hip_check(hipStreamSynchronize(md.last_stream), "sync");
     if (st != WF_OK) return st;
     md.ws.reset();
+    md.ws_clean = false;
     return WF_OK;
     ABI_GUARD_END
 }

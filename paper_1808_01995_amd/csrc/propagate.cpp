@@ -344,13 +344,19 @@ struct FieldPool {
     static int64_t bytes_for(const Layout& L, int n) {
         return (int64_t)n * ((L.alloc_elems + 63) / 64 * 64) * 4 + 256;
     }
-    // n zeroed buffers in `buf` (grown if too small; work enqueued on s before
-    // this call may still read the old contents, so growing waits for it)
-    wf_status carve(DevBuf& buf, const Layout& L, int n, hipStream_t s) {
+    // n buffers in `buf` (grown if too small; work enqueued on s before this
+    // call may still read the old contents, so growing waits for it). All n
+    // are zeroed, unless `clean` says that every ghost plane in `buf` is
+    // still zero from an earlier carve (kernels never write ghost planes):
+    // then only the first nzero buffers are, the rest being written before
+    // they are read.
+    wf_status carve(DevBuf& buf, const Layout& L, int n, hipStream_t s, int nzero = -1,
+                    bool* clean = nullptr) {
         stride = (L.alloc_elems + 63) / 64 * 64;
         off = L.ghost_off;
         count = n;
         const int64_t need = bytes_for(L, n);
+        bool fresh = false;
         if (buf.bytes < need) {
             wf_status st = hip_check(hipStreamSynchronize(s), "sync");
             if (st == WF_OK) {
@@ -358,9 +364,17 @@ struct FieldPool {
                 st = buf.alloc(need);
             }
             if (st != WF_OK) return st;
+            fresh = true;
         }
         base = buf.f();
-        return hip_check(launch_fill(base, need / 4, 0.0f, s), "fill");
+        if (nzero < 0 || !clean) return hip_check(launch_fill(base, need / 4, 0.0f, s), "fill");
+        if (fresh || !*clean) {
+            WF_TRY(hip_check(launch_fill(base, buf.bytes / 4, 0.0f, s), "fill"));
+            *clean = true;
+            return WF_OK;
+        }
+        return hip_check(launch_fill(base, std::min<int64_t>(need / 4, (int64_t)nzero * stride), 0.0f, s),
+                         "fill");
     }
     wf_status alloc(const Layout& L, int n, hipStream_t s) { return carve(own, L, n, s); }
     float* at(int i) const { return base + (int64_t)i * stride + off; }
@@ -396,13 +410,17 @@ wf_status gradient_boundary(Model& md, double dt, int nt, const PointSet& src, c
     if (budget > 0) cap = std::min<int64_t>(cap, budget);
     const int64_t need = held + (4 + strip_fields) * fb;
     if (need > cap) return fail(WF_E_BUDGET, "gradient needs %lld bytes, %lld available", (long long)need, (long long)cap);
+    // A, B, V1, V2 start at zero; the slabs overwrite ghost planes of the
+    // workspace, which the next carve must therefore clear again
     FieldPool pool;
-    WF_TRY(pool.carve(md.ws, L, (int)(4 + strip_fields), s));
+    WF_TRY(pool.carve(md.ws, L, (int)(4 + strip_fields), s, 4, &md.ws_clean));
+    md.ws_clean = false;
     float* A = pool.at(0);    // u^n in the forward sweep, u^{n+1} in the reverse sweep
     float* B = pool.at(1);
     float* V1 = pool.at(2);   // v^{n+1}
     float* V2 = pool.at(3);   // v^{n+2}, overwritten by v^n
-    float* strips = pool.raw(4);   // row n: the slabs of u^n (row 0 stays zero)
+    float* strips = pool.raw(4);   // row n: the slabs of u^n (row 0: u^0 = 0)
+    WF_TRY(hip_check(launch_fill(strips, per, 0.0f, s), "fill"));
 
     Injector qinj, rinj;
     WF_TRY(qinj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
@@ -505,10 +523,13 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
 
     // one carve of the model's workspace (kept for the next call: allocating
     // tens of GB again costs seconds) holds the pool and the adjoint pair
+    // the adjoint pair and the first two forward buffers (u^0 = u^{-1} = 0)
+    // start at zero; every other buffer is written before it is read
     FieldPool pool;
-    WF_TRY(pool.carve(md.ws, L, nbuf + 2, s));
-    float* V1 = pool.at(nbuf);       // v^{n+1}
-    float* V2 = pool.at(nbuf + 1);   // v^{n+2}, overwritten by v^n
+    WF_TRY(pool.carve(md.ws, L, nbuf + 2, s, 4, &md.ws_clean));
+    float* V1 = pool.at(0);   // v^{n+1}
+    float* V2 = pool.at(1);   // v^{n+2}, overwritten by v^n
+    auto F = [&](int i) { return pool.at(2 + i); };   // forward buffer i
     Injector qinj, rinj;   // sources in forward steps, residual in adjoint steps
     WF_TRY(qinj.prepare(md, src, p, src_wav, nt, md.d_inc[0], s));
     bool resid_ready = obs == nullptr;
@@ -554,11 +575,11 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
     if (store_all) {
         // buffer 0 is zero and stands for both u^0 and u^{-1}; buffer j holds u^j
         for (int64_t n = 0; n + 1 < nt; ++n) {
-            const float* cur = pool.at((int)n);
-            const float* old = pool.at((int)std::max<int64_t>(n - 1, 0));
-            WF_TRY(forward_step(n, cur, old, pool.at((int)(n + 1))));
+            const float* cur = F((int)n);
+            const float* old = F((int)std::max<int64_t>(n - 1, 0));
+            WF_TRY(forward_step(n, cur, old, F((int)(n + 1))));
         }
-        for (int64_t n = nt - 2; n >= 0; --n) WF_TRY(reverse_step(n, pool.at((int)(n + 1))));
+        for (int64_t n = nt - 2; n >= 0; --n) WF_TRY(reverse_step(n, F((int)(n + 1))));
     } else {
         std::vector<RevolveAction> acts;
         WF_TRY(revolve_schedule(l, snaps, acts));
@@ -573,7 +594,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
             return -1;
         };
         // x_0: u^0 = u^{-1} = 0 (the pool starts zeroed), one forward step injecting q^0
-        WF_TRY(forward_step(0, pool.at(0), pool.at(1), pool.at(1)));
+        WF_TRY(forward_step(0, F(0), F(1), F(1)));
         bn = 1;
         bo = 0;
         int64_t pos = 0;
@@ -585,7 +606,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
                         // forward step F_{i+1}: u^{i+2} from u^{i+1} (bn), u^i (bo), q^{i+1}
                         int out = pin[bo] == 0 ? bo : take_free(bn, bo);
                         if (out < 0) return fail(WF_E_STATE, "revolve: buffer pool exhausted");
-                        WF_TRY(forward_step(i + 1, pool.at(bn), pool.at(bo), pool.at(out)));
+                        WF_TRY(forward_step(i + 1, F(bn), F(bo), F(out)));
                         bo = bn;
                         bn = out;
                     }
@@ -604,7 +625,7 @@ wf_status gradient_core(Model& md, double dt, int nt, const PointSet& src, const
                     break;
                 case RevolveAction::REVERSE:
                     if (a.at != pos) return fail(WF_E_STATE, "revolve: reverse step out of place");
-                    WF_TRY(reverse_step(a.at, pool.at(bn)));
+                    WF_TRY(reverse_step(a.at, F(bn)));
                     break;
                 case RevolveAction::FREE:
                     --pin[slot[(size_t)a.arg].first];

@@ -127,6 +127,7 @@ struct Model : public wf_model {
     wf::DevBuf d_m, d_kap, d_u[2], d_etax, d_etay, d_etaz, d_scratch;
     wf::DevBuf d_inc[2];   // precomputed injection increments (grow-only, stream-ordered reuse)
     wf::DevBuf ws;         // gradient workspace (checkpoint pool + adjoint pair), kept between calls
+    bool ws_clean = false; // every ghost plane in ws is zero
     float m_min = 0.f, m_max = 0.f;
     double kap_dt = -1.0;
     std::vector<PCache> pcache;
