@@ -45,13 +45,16 @@ class Propagator:
 
     shape: physical grid (2 or 3 axes); spacing in metres; nbl damping-layer
     width; space_order k in 4..16; c_ref the damping reference velocity
-    (default: the largest velocity of the model at creation, then frozen).
+    (default: the largest velocity of the model at creation, then frozen);
+    origin the physical origin (m); R and eta_power the damping profile's
+    nominal reflection coefficient and power (0: 1e-3 and 2).
     """
 
     def __init__(self, v_phys=None, spacing: Sequence[float] = (10.0, 10.0, 10.0), nbl: int = 40,
                  space_order: int = 8, c_ref: Optional[float] = None,
                  origin: Optional[Sequence[float]] = None, m: Optional[torch.Tensor] = None,
-                 shape: Optional[Sequence[int]] = None, device="cuda"):
+                 shape: Optional[Sequence[int]] = None, device="cuda", R: float = 0.0,
+                 eta_power: int = 0):
         if m is None:
             if v_phys is None:
                 raise ValueError("give v_phys or m")
@@ -71,7 +74,8 @@ class Propagator:
         self.nbl = int(nbl)
         self.space_order = int(space_order)
         self.c_ref = float(c_ref)
-        self.geom = make_geom(self.shape, self.spacing, self.nbl, self.space_order, self.c_ref, origin)
+        self.geom = make_geom(self.shape, self.spacing, self.nbl, self.space_order, self.c_ref, origin,
+                              R, eta_power)
         self.comp_shape, self.npoints = _abi.wf_geom_shape(self.geom)
         if tuple(m.shape) != self.comp_shape:
             raise ValueError("m has shape %s, expected %s" % (tuple(m.shape), self.comp_shape))
