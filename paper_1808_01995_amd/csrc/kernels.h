@@ -106,8 +106,6 @@ TileShape step_tile(int ndim, int tile);
 // Choose the tile shape and the x-chunking (ntz/nty/nchunks/nblocks/cx); a
 // positive cx_request forces the chunk length, tile_request >= 0 the shape.
 void step_plan(StepParams& p, int ndim, int half, int mode, int cx_request, int tile_request);
-// Threads per block of the step kernel for a dimension and tile shape.
-int step_threads(int ndim, int tile);
 hipError_t launch_step(const StepParams& p, int ndim, int half, int mode, hipStream_t s);
 
 // Sparse injection at unique nodes (deterministic, no atomics):
@@ -161,7 +159,6 @@ hipError_t launch_unpitch(const float* src, float* dst, int nx, int ny, int nz, 
 hipError_t launch_pitch(const float* src, float* dst, int nx, int ny, int nz, int64_t sx,
                         int64_t sy, hipStream_t s);
 hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s);
-hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
 // count of non-finite values in x[0..n) added to *count
 hipError_t launch_count_nonfinite(const float* x, int64_t n, unsigned int* count, hipStream_t s);
 // r = d - d_obs (r may alias d); partial[b] = sum over block b of r^2 in FP64,

@@ -505,17 +505,6 @@ __global__ void k_fill(float* __restrict__ d, int64_t n, float v) {
         d[i] = v;
 }
 
-__global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, int64_t n) {
-    const int64_t n4 = n / 4;
-    const float4* s4 = reinterpret_cast<const float4*>(s);
-    float4* d4 = reinterpret_cast<float4*>(d);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
-         i += (int64_t)gridDim.x * blockDim.x)
-        d4[i] = s4[i];
-    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        d[i] = s[i];
-}
 
 __global__ void k_residual(const float* d, const float* __restrict__ d_obs, float* r, int64_t n,
                            double* partial) {
@@ -699,11 +688,6 @@ int step_capacity(int ndim, int half, int tile, int mode) {
 
 }  // namespace
 
-int step_threads(int ndim, int tile) {
-    const TileShape t = step_tile(ndim, tile);
-    return t.bz * t.by;
-}
-
 TileShape step_tile(int ndim, int tile) {
     if (ndim == 3) return kTiles3[tile == 1 ? 1 : 0];
     return kTile2;
@@ -839,12 +823,6 @@ hipError_t launch_pitch(const float* src, float* dst, int nx, int ny, int nz, in
 hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid_1d(n, 256)), dim3(256), 0, s, dst, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy, dim3(grid_1d(n / 4 + 1, 256)), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 
