@@ -52,6 +52,22 @@ def test_2d_all_orders(k):
     assert rel_l2(d, P.oracle_forward()) <= 1e-4
 
 
+@pytest.mark.parametrize("k", [4, 8, 16])
+def test_2d_long_rows(k):
+    """Rows of 1106 nodes select the 512-wide 2D tile (three tiles, the last
+    ragged); forward and adjoint against the oracle."""
+    P = make_problem((45, 1090), 8, k, 120, seed=80 + k, nrec=70)
+    d = _gpu_forward(P).cpu().numpy()
+    err = rel_l2(d, P.oracle_forward())
+    y = noise(P.nt, P.rec_xyz.shape[0], P.dt, 15.0, 6)
+    prop = P.propagator()
+    x = prop.adjoint(P.dt, P.nt, P.rec_xyz, torch.from_numpy(y.astype(np.float32)).cuda(),
+                     P.src_xyz).cpu().numpy()
+    err_a = rel_l2(x, P.oracle_adjoint(y.astype(np.float32).astype(np.float64)))
+    print("2D long rows k=%d: forward %.2e adjoint %.2e" % (k, err, err_a))
+    assert err <= 1e-4 and err_a <= 1e-4
+
+
 @pytest.mark.parametrize("k", [4, 8, 12, 16])
 def test_3d_orders_ragged_tiles(k):
     """(y, z) tiles of 16 x 64 and x chunks: 71 x 37 x 93 computational nodes
