@@ -137,6 +137,39 @@ def graph_c1(torch, shots=20):
     return res
 
 
+def large_2d(torch, n=8192, orders=(4, 8, 12), steps=300):
+    """Large 2D grids: n^2 physical + 40-node layer, v = 2 km/s, one source,
+    256 receivers at 20 m; GPts/s and the step kernel's algorithmic bandwidth
+    (HIP events around every 4th launch)."""
+    from paper_1808_01995_amd import Propagator, _abi
+    from synthetic import ricker
+    res = []
+    for so in orders:
+        prop = Propagator(np.full((n, n), 2.0, dtype=np.float32), spacing=(10.0, 10.0), nbl=40,
+                          space_order=so)
+        dt = 0.5 * prop.critical_dt()
+        nt = steps + 1
+        ext = (n - 1) * 10.0
+        src = np.array([[ext / 2, 20.0]])
+        rec = np.stack([np.linspace(0, ext, 256), np.full(256, 20.0)], 1)
+        q = torch.from_numpy(ricker(nt, dt, 10.0)[:, None].astype(np.float32)).cuda()
+        out = torch.empty((nt, 256), device="cuda")
+        prop.forward(dt, 21, src, q[:21].contiguous(), rec, rec_out=out[:21])
+        _abi.wf_profile_read(0, reset=True)
+        _abi.wf_profile_enable(4)
+        el, _ = _timed(torch, lambda: prop.forward(dt, nt, src, q, rec, rec_out=out))
+        _abi.wf_profile_enable(False)
+        ms, k = _abi.wf_profile_read(0, reset=True)
+        us = ms / max(k, 1) * 1e3
+        gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
+        res.append({"space_order": so, "gpts": round(prop.npoints * steps / el / 1e9, 1),
+                    "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs),
+                    "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3)})
+        prop.close()
+        log("2d %d so%d: %s" % (n, so, res[-1]))
+    return {"workload": "%d^2 physical (%d^2 computational), %d updates" % (n, n + 80, steps), "orders": res}
+
+
 def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
     """512^3 physical (592^3 computational), two-layer 1.5/2.5 km/s, one
     shot per order: GPts/s and the step kernel's algorithmic bandwidth."""
@@ -368,7 +401,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
     ap.add_argument("--rows", default="",
-                    help="comma list of further rows to measure: c1,c3,c4,born,fwi,serve (or all)")
+                    help="comma list of further rows to measure: c1,2d,c3,c4,born,fwi,serve (or all)")
     ap.add_argument("--updates", type=int, default=None,
                     help="shorter shots (profiling runs only; the benchmark uses 1000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -490,9 +523,11 @@ def main():
     prop.close()
     rows = set(x for x in args.rows.split(",") if x)
     if "all" in rows:
-        rows = {"c1", "c3", "c4", "born", "fwi", "serve"}
+        rows = {"c1", "2d", "c3", "c4", "born", "fwi", "serve"}
     if "c1" in rows:
         out["c1_graph"] = graph_c1(torch)
+    if "2d" in rows:
+        out["large_2d"] = large_2d(torch)
     if "c3" in rows:
         out["c3_sweep"] = sweep_c3(torch)
     if "c4" in rows:
