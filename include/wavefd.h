@@ -1,7 +1,9 @@
 /*
  * wavefd.h - C ABI of an MI355X (gfx950) explicit finite-difference acoustic
  * propagator: forward modelling, its exact discrete adjoint, the adjoint-state
- * gradient with optimal checkpointing, and a continuous-batching serving engine.
+ * gradient with optimal checkpointing or boundary-wavefield reconstruction,
+ * the multi-shot FWI gradient and fixed-step update, linearised (Born)
+ * modelling, and a continuous-batching serving engine.
  *
  * The operations follow arxiv 1808.01995 (Louboutin et al., Devito v3.1.0):
  *   - PDE: m u_tt - Lap u + eta u_t = q, m = 1/c^2 the squared slowness
@@ -21,8 +23,12 @@
  *     Section "Temporal discretization"; eq. Adj);
  *   - gradient of Phi = 1/2 ||P_r u - d||^2 (eqs. AS, Grad):
  *         g = - sum_{j=1}^{nt-1} u^j (v^{j-1} - 2 v^j + v^{j+1}) / dt^2,
- *     with the forward wavefield kept by optimal (revolve) checkpointing
- *     (Section "Discrete adjoint wave-equation and FWI gradient").
+ *     with the forward wavefield kept by optimal (revolve) checkpointing or
+ *     rebuilt from stored boundary values (Section "Discrete adjoint
+ *     wave-equation and FWI gradient");
+ *   - FWI: the objective and gradient summed over source experiments and a
+ *     fixed-step update (Section "FWI using Devito operators");
+ *   - J dm, the Jacobian of eq. Grad applied to a model perturbation.
  *
  * Conventions shared by every call:
  *   - Physical grid n[0..ndim-1] nodes with spacing h (m); a damping layer of
