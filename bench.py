@@ -413,7 +413,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(shots are independent; see the design notes for how it would shard)",
               file=sys.stderr)
         sys.exit(2)

@@ -148,7 +148,7 @@ def test_graph_cache_eviction():
     bufs = [torch.empty_like(rec) for _ in range(6)]
     n0 = _launches(prop)
     outs = []
-    for rnd in range(3):
+    for _pass in range(3):
         for b in bufs:
             b.fill_(float("nan"))
             _abi().wf_forward(prop.handle, P.dt, P.nt, P.src_xyz, q, P.rec_xyz, b)
@@ -156,8 +156,8 @@ def test_graph_cache_eviction():
             outs.append(b.clone())
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
-    # round 0: eager; round 1: six captures (evicting the two oldest);
-    # round 2: buffers 0, 1 evicted -> not cached; recent eager signatures
+    # pass 0: eager; pass 1: six captures (evicting the two oldest);
+    # pass 2: buffers 0, 1 evicted -> not cached; recent eager signatures
     # were consumed by their capture, so they run eagerly again and the LRU
     # loops 2..5 replay
     assert _launches(prop) == n0 + 6 + 4
