@@ -240,3 +240,30 @@ class ModelingFunction(torch.autograd.Function):
 def model_data(m: torch.Tensor, prop: Propagator, dt: float, nt: int, src_xyz, src_wav, rec_xyz,
                n_checkpoints: int = 0) -> torch.Tensor:
     return ModelingFunction.apply(m, prop, dt, nt, src_xyz, src_wav, rec_xyz, n_checkpoints)
+
+
+class FWIObjective(torch.autograd.Function):
+    """Phi(m) = sum_s 1/2 ||F_s(m) - d_obs,s||^2 as a differentiable scalar of
+    the squared slowness on the computational grid (the multi-shot objective
+    of Section "FWI using Devito operators"). The forward pass already forms
+    the summed gradient (two wave solves per shot, wf_fwi_gradient); backward
+    scales it by the incoming gradient. shots: sequence of (src_xyz, src_wav,
+    rec_xyz, d_obs)."""
+
+    @staticmethod
+    def forward(ctx, m: torch.Tensor, prop: Propagator, dt: float, nt: int, shots,
+                n_checkpoints: int = 0):
+        prop.set_m(m.detach())
+        phi, g = prop.fwi_gradient(dt, nt, shots, n_checkpoints)
+        ctx.save_for_backward(g)
+        return torch.tensor(phi, dtype=torch.float64, device=m.device)
+
+    @staticmethod
+    def backward(ctx, grad_phi: torch.Tensor):
+        (g,) = ctx.saved_tensors
+        return (grad_phi.to(torch.float32) * g), None, None, None, None, None
+
+
+def fwi_objective(m: torch.Tensor, prop: Propagator, dt: float, nt: int, shots,
+                  n_checkpoints: int = 0) -> torch.Tensor:
+    return FWIObjective.apply(m, prop, dt, nt, shots, n_checkpoints)

@@ -168,3 +168,30 @@ def test_model_update_and_descent():
     phis.append(phi_last)
     print("fwi misfit by iteration:", phis)
     assert all(b < a for a, b in zip(phis, phis[1:]))
+
+
+def test_fwi_objective_autograd():
+    """The multi-shot objective as a torch.autograd.Function on the physical
+    grid (replicate-pad adjoint folds the layer): its value and gradient equal
+    the sum of per-shot ModelingFunction losses and their autograd gradient."""
+    from paper_1808_01995_amd import fwi_objective, model_data, pad_replicate
+    S = _survey(nshots=2, steps=100)
+    prop = _prop(S)
+    shots = _gpu_shots(S)
+    nbl = S["nbl"]
+    inner = tuple(slice(nbl, nbl + n) for n in S["shape_phys"])
+    m_phys = torch.from_numpy(np.ascontiguousarray(S["m0"][inner])).cuda().requires_grad_(True)
+    phi = fwi_objective(pad_replicate(m_phys, nbl), prop, S["dt"], S["nt"], shots)
+    phi.backward()
+    g1 = m_phys.grad.clone()
+    m2 = m_phys.detach().clone().requires_grad_(True)
+    loss = 0.0
+    for s, q, r, d_obs in shots:
+        d = model_data(pad_replicate(m2, nbl), prop, S["dt"], S["nt"], s, q, r)
+        loss = loss + 0.5 * ((d.double() - d_obs.double()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert abs(float(phi) - float(loss)) <= 1e-9 * float(loss)
+    err = float((g1.double() - m2.grad.double()).norm() / m2.grad.double().norm())
+    print("FWIObjective vs ModelingFunction gradient rel %.2e" % err)
+    assert err <= 1e-5
