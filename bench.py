@@ -391,6 +391,22 @@ def profile_kernels(torch, steps=400):
     print(json.dumps({"profile_kernels": "done", "grid": list(p0.comp_shape), "updates": steps}), flush=True)
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10) -> float:
+    """Read + write GB/s of a plain device-to-device copy (the STREAM-copy
+    analogue the step kernel's bandwidth is compared with)."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    del a, b
+    return 2.0 * nbytes / el / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,6 +487,8 @@ def main():
     g_launches = _abi.wf_model_graph_launches(prop.handle) - g0
     _abi.wf_graph_enable(False)
 
+    copy_gbs = copy_bandwidth(torch)
+
     ms_per_shot = el / args.steps * 1e3
     updates = npts * c.steps
     gpts = updates / (ms_per_shot * 1e-3) / 1e9
@@ -509,7 +527,9 @@ def main():
                      "kernel": "k_step3d<M=4> (fused stencil + damping + time update)",
                      "avg_kernel_ms": round(avg_kernel_ms, 5), "timed_launches": k_n,
                      "launches_in_timed_region": args.steps * c.steps,
-                     "algorithmic_bytes_per_launch": BYTES_PER_POINT * npts},
+                     "algorithmic_bytes_per_launch": BYTES_PER_POINT * npts,
+                     "measured_copy_GBs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
     }
 
     if args.extras:
