@@ -170,6 +170,42 @@ def large_2d(torch, n=8192, orders=(4, 8, 12), steps=300):
     return {"workload": "%d^2 physical (%d^2 computational), %d updates" % (n, n + 80, steps), "orders": res}
 
 
+def slab_share(torch, ngpu=8, steps=300, so=8):
+    """One GPU's share of the 592^3 grid split into x-slabs over `ngpu` GPUs:
+    592/ngpu planes plus M halo planes on each side (the planes a neighbour
+    would send each update), at the real shape; the step kernel's time per
+    update against the time the halo faces would take over one xGMI link."""
+    from paper_1808_01995_amd import Propagator, _abi
+    from synthetic import ricker
+    half = so // 2
+    nx = 592 // ngpu + 2 * half
+    shape = (nx, 592, 592)
+    prop = Propagator(np.full(shape, 2.0, dtype=np.float32), spacing=(10.0,) * 3, nbl=0, space_order=so)
+    dt = 0.5 * prop.critical_dt()
+    nt = steps + 1
+    src = np.array([[nx * 5.0, 2955.0, 20.0]])
+    rec = np.stack([np.full(512, nx * 5.0), np.linspace(0, 5910, 512), np.full(512, 20.0)], 1)
+    q = torch.from_numpy(ricker(nt, dt, 15.0)[:, None].astype(np.float32)).cuda()
+    out = torch.empty((nt, 512), device="cuda")
+    prop.forward(dt, 21, src, q[:21].contiguous(), rec, rec_out=out[:21])
+    _abi.wf_profile_read(0, reset=True)
+    _abi.wf_profile_enable(4)
+    el, _ = _timed(torch, lambda: prop.forward(dt, nt, src, q, rec, rec_out=out))
+    _abi.wf_profile_enable(False)
+    ms, k = _abi.wf_profile_read(0, reset=True)
+    us = ms / max(k, 1) * 1e3
+    face = half * 592 * 592 * 4
+    res = {"workload": "x-slab of 592^3 for %d GPUs: %dx592x592 nodes (%d planes + 2 x %d halo planes), order %d"
+                       % (ngpu, nx, 592 // ngpu, half, so),
+           "step_kernel_us": round(us, 1), "us_per_update": round(el / steps * 1e6, 1),
+           "frac_8TBs": round(BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 3),
+           "halo_face_MB": round(face / 1e6, 2),
+           "face_transfer_us_at_153GBs": round(face / 153e9 * 1e6, 1)}
+    prop.close()
+    log("slab: %s" % res)
+    return res
+
+
 def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
     """512^3 physical (592^3 computational), two-layer 1.5/2.5 km/s, one
     shot per order: GPts/s and the step kernel's algorithmic bandwidth."""
@@ -417,7 +453,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
     ap.add_argument("--rows", default="",
-                    help="comma list of further rows to measure: c1,2d,c3,c4,born,fwi,serve (or all)")
+                    help="comma list of further rows to measure: c1,2d,c3,slab,c4,born,fwi,serve (or all)")
     ap.add_argument("--updates", type=int, default=None,
                     help="shorter shots (profiling runs only; the benchmark uses 1000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -543,13 +579,15 @@ def main():
     prop.close()
     rows = set(x for x in args.rows.split(",") if x)
     if "all" in rows:
-        rows = {"c1", "2d", "c3", "c4", "born", "fwi", "serve"}
+        rows = {"c1", "2d", "c3", "slab", "c4", "born", "fwi", "serve"}
     if "c1" in rows:
         out["c1_graph"] = graph_c1(torch)
     if "2d" in rows:
         out["large_2d"] = large_2d(torch)
     if "c3" in rows:
         out["c3_sweep"] = sweep_c3(torch)
+    if "slab" in rows:
+        out["slab_share"] = slab_share(torch)
     if "c4" in rows:
         out["c4_gradient"] = gradient_c4(torch)
     if "born" in rows:
