@@ -65,17 +65,18 @@ struct StepParams {
     float* smp_out;      // NULL: no sampling
     int smp_n, smp_per;
 
-    // Fused injection into `out`: nodes grouped by block (inj_blk, nblocks+1
-    // offsets), inside a block by (thread, x); thread t of block b owns the
-    // node range inj_thr[b*NT + t]. inj_inc holds this step's increments.
+    // Fused injection into `out`: entries grouped by block (inj_blk, nblocks+1
+    // offsets), inside a block by (thread, x); an entry is one (thread, plane)
+    // pair with the increments of its 4 z nodes (zero where no node), and
+    // thread t of block b owns the entry range inj_thr[b*NT + t]. inj_inc
+    // holds this step's increments, one float4 per entry.
     const int* inj_blk;  // NULL: no injection
     const int2* inj_thr;
     const int* inj_x;
-    const int* inj_comp;
-    const float* inj_inc;
+    const float4* inj_inc;
 };
 
-// Largest number of injection nodes a block can stage in LDS.
+// Largest number of injection entries a block can stage in LDS.
 constexpr int kInjCap = 1024;
 
 // One grid of a batched step launch (see k_step_batch).

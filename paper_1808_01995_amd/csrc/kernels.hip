@@ -20,6 +20,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <climits>
 #include <cstdlib>
 #include <mutex>
 
@@ -129,8 +130,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
     constexpr int JZ = (NHZ + NT - 1) / NT;
     __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];
     __shared__ int inj_xl[kInjCap];
-    __shared__ int inj_cl[kInjCap];
-    __shared__ float inj_vl[kInjCap];
+    __shared__ float4 inj_vl[kInjCap];
 
     const int r = xcd_remap(bidx, p.nblocks);
     if (r >= p.nblocks) return;
@@ -198,18 +198,26 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
         eyz[i] = (own && z + i < p.nz) ? ((D3 ? p.etay[y] : 0.0f) + p.etaz[z + i]) : 0.0f;
 
     // this block's injection nodes -> LDS (read only after the first barrier)
-    int inj_i = 0, inj_e = 0;
+    int inj_i = 0, inj_e = 0, inj_nx = INT_MAX;
+    float4 inj_nv = zero4();
     if (p.inj_blk) {
         const int b0 = p.inj_blk[r], b1 = p.inj_blk[r + 1];
         if (b1 > b0) {
             for (int i = tid; i < b1 - b0; i += NT) {
                 inj_xl[i] = p.inj_x[b0 + i];
-                inj_cl[i] = p.inj_comp[b0 + i];
                 inj_vl[i] = p.inj_inc[b0 + i];
             }
             const int2 rg = p.inj_thr[(int64_t)r * NT + tid];
             inj_i = rg.x - b0;
             inj_e = rg.y - b0;
+            // the thread's next entry (plane and increments) lives in
+            // registers: a plane without one costs one compare, and the LDS
+            // reads of the following entry are not waited for in the plane
+            // that issues them
+            if (inj_i < inj_e) {
+                inj_nx = p.inj_x[rg.x];
+                inj_nv = p.inj_inc[rg.x];
+            }
         }
     }
 
@@ -349,31 +357,30 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
                         set_comp(g2, i, -comp(uf, i) * lapt);
                     }
                 }
-                // sources owned by this thread at this plane (rare, divergent)
-                // (at most one node per component; components are selected
-                // arithmetically and the loop has a fixed trip count, so neither
-                // the plane loop's unrolling nor register allocation is disturbed)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (!(inj_i < inj_e && inj_xl[inj_i] == x)) break;
-                    const int ci = inj_cl[inj_i];
-                    const float inc = inj_vl[inj_i];
-                    const float i0 = ci == 0 ? inc : 0.0f, i1 = ci == 1 ? inc : 0.0f;
-                    const float i2 = ci == 2 ? inc : 0.0f, i3 = ci == 3 ? inc : 0.0f;
-                    o.x += i0; o.y += i1; o.z += i2; o.w += i3;
+                // the source entry owned by this thread at this plane (rare,
+                // divergent; nodes without a source have a zero increment)
+                if (inj_nx == x) {
+                    const float4 inc = inj_nv;
+                    o.x += inc.x; o.y += inc.y; o.z += inc.z; o.w += inc.w;
                     if (IMG) {
-                        g2.x -= uf.x * i0 * p.idt2;
-                        g2.y -= uf.y * i1 * p.idt2;
-                        g2.z -= uf.z * i2 * p.idt2;
-                        g2.w -= uf.w * i3 * p.idt2;
+                        g2.x -= uf.x * inc.x * p.idt2;
+                        g2.y -= uf.y * inc.y * p.idt2;
+                        g2.z -= uf.z * inc.z * p.idt2;
+                        g2.w -= uf.w * inc.w * p.idt2;
                     }
                     if (BSRC) {
-                        g2.x -= uf.x * i0;
-                        g2.y -= uf.y * i1;
-                        g2.z -= uf.z * i2;
-                        g2.w -= uf.w * i3;
+                        g2.x -= uf.x * inc.x;
+                        g2.y -= uf.y * inc.y;
+                        g2.z -= uf.z * inc.z;
+                        g2.w -= uf.w * inc.w;
                     }
                     ++inj_i;
+                    if (inj_i < inj_e) {
+                        inj_nx = inj_xl[inj_i];
+                        inj_nv = inj_vl[inj_i];
+                    } else {
+                        inj_nx = INT_MAX;
+                    }
                 }
                 if (own) {
                     const int64_t base = (int64_t)x * sx;
@@ -419,7 +426,7 @@ __global__ void __launch_bounds__(BZ * BY) k_step_batch(const BatchJob* __restri
         p.old = J.buf1;
         p.out = J.buf1;
     }
-    if (p.inj_blk) p.inj_inc += n * J.inj_stride;
+    if (p.inj_blk) p.inj_inc += n * (J.inj_stride / 4);
     if (p.smp_out) p.smp_out += n * J.smp_stride;
     step_body<D3, M, BZ, BY, PF, kModePlain>(p, b - J.block_begin);
 }

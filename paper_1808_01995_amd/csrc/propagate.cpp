@@ -131,8 +131,7 @@ struct Injector {
         p.inj_blk = fz->blk.as<int>();
         p.inj_thr = fz->thr.as<int2>();
         p.inj_x = fz->x.as<int>();
-        p.inj_comp = fz->comp.as<int>();
-        p.inj_inc = inc + row * fz->nnodes;
+        p.inj_inc = reinterpret_cast<const float4*>(inc + row * fz->nnodes);
     }
     // after the step: the separate kernel when not fused
     wf_status after(const Model& md, int64_t row, float* field, float* grad, const float* ufwd,

@@ -352,43 +352,58 @@ wf_status PointSet::fused(const Layout& L, const StepParams& p, const FusedInj**
         if (a.x != b.x) return a.x < b.x;
         return a.comp < b.comp;
     });
-    std::vector<int> blk((size_t)p.nblocks + 1, 0), xs, comps, segs(1, 0), pts;
+    // entries: one per (block, thread, plane), 4 increment slots each (the
+    // thread's 4 z nodes; an empty slot has no terms and so a zero increment)
+    std::vector<int> blk((size_t)p.nblocks + 1, 0), xs, segs(1, 0), pts;
     std::vector<int2> thr((size_t)p.nblocks * NT, make_int2(0, 0));
     std::vector<int64_t> offs;
     std::vector<float> etas, ws;
     f->ok = true;
     size_t i = 0;
+    int ne = 0;
     for (int64_t b = 0; b < p.nblocks; ++b) {
-        blk[(size_t)b] = (int)i;
-        const size_t b0 = i;
+        blk[(size_t)b] = ne;
+        const int e_b0 = ne;
         while (i < own.size() && own[i].blk == b) {
-            const size_t t0 = i;
+            const int t0 = ne;
             const int tid = own[i].tid;
             while (i < own.size() && own[i].blk == b && own[i].tid == tid) {
-                const Own& w = own[i];
-                xs.push_back(w.x);
-                comps.push_back(w.comp);
-                offs.push_back(h_noff[(size_t)w.node]);
-                etas.push_back(h_neta[(size_t)w.node]);
-                for (int e = h_seg[(size_t)w.node]; e < h_seg[(size_t)w.node + 1]; ++e) {
-                    pts.push_back(h_ept[(size_t)e]);
-                    ws.push_back(h_ew[(size_t)e]);
+                const int x = own[i].x;
+                int node_of[4] = {-1, -1, -1, -1};
+                while (i < own.size() && own[i].blk == b && own[i].tid == tid && own[i].x == x) {
+                    node_of[own[i].comp] = own[i].node;
+                    ++i;
                 }
-                segs.push_back((int)pts.size());
-                ++i;
+                xs.push_back(x);
+                for (int c = 0; c < 4; ++c) {
+                    const int k = node_of[c];
+                    if (k >= 0) {
+                        offs.push_back(h_noff[(size_t)k]);
+                        etas.push_back(h_neta[(size_t)k]);
+                        for (int e = h_seg[(size_t)k]; e < h_seg[(size_t)k + 1]; ++e) {
+                            pts.push_back(h_ept[(size_t)e]);
+                            ws.push_back(h_ew[(size_t)e]);
+                        }
+                    } else {
+                        offs.push_back(0);   // any valid node: its coefficient multiplies 0
+                        etas.push_back(0.0f);
+                    }
+                    segs.push_back((int)pts.size());
+                }
+                ++ne;
             }
-            thr[(size_t)(b * NT + tid)] = make_int2((int)t0, (int)i);
+            thr[(size_t)(b * NT + tid)] = make_int2(t0, ne);
         }
-        if (i - b0 > (size_t)kInjCap) f->ok = false;
+        if (ne - e_b0 > kInjCap) f->ok = false;
     }
-    blk[(size_t)p.nblocks] = (int)i;
-    f->nnodes = (int)i;
+    blk[(size_t)p.nblocks] = ne;
+    f->nentries = ne;
+    f->nnodes = 4 * ne;
     wf_status st;
     if (f->ok) {
         if ((st = f->blk.upload(blk.data(), (int64_t)blk.size() * 4)) != WF_OK ||
             (st = f->thr.upload(thr.data(), (int64_t)thr.size() * 8)) != WF_OK ||
             (st = f->x.upload(xs.data(), (int64_t)xs.size() * 4)) != WF_OK ||
-            (st = f->comp.upload(comps.data(), (int64_t)comps.size() * 4)) != WF_OK ||
             (st = f->off.upload(offs.data(), (int64_t)offs.size() * 8)) != WF_OK ||
             (st = f->eta.upload(etas.data(), (int64_t)etas.size() * 4)) != WF_OK ||
             (st = f->seg.upload(segs.data(), (int64_t)segs.size() * 4)) != WF_OK ||

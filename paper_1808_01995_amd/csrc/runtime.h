@@ -70,14 +70,16 @@ struct Layout {
 };
 
 // Injection nodes of a point set arranged for the fused step kernel of one
-// launch plan: nodes grouped by block, by owning thread and by x inside a
-// block, plus everything the increment kernel needs in that order.
+// launch plan: entries (one per owning thread and plane, holding that
+// thread's 4 z nodes) grouped by block, by thread and by x inside a block,
+// plus everything the increment kernel needs per node slot in that order.
 struct FusedInj {
     int64_t key[6] = {0, 0, 0, 0, 0, 0};   // plan: tile, ntz, nty, cx, nchunks, NT
     bool ok = false;                       // false: a block exceeds the LDS cap
-    int nnodes = 0;
-    DevBuf blk, thr, x, comp;              // block offsets, per-thread ranges, plane, component
-    DevBuf off, eta, seg, pt, w;           // increment inputs in the same order
+    int nentries = 0;                      // (thread, plane) entries
+    int nnodes = 0;                        // increment slots: 4 per entry
+    DevBuf blk, thr, x;                    // block offsets, per-thread ranges, entry plane
+    DevBuf off, eta, seg, pt, w;           // increment inputs per slot (empty slots: no terms)
 };
 
 // Sparse points of one acquisition: a gather table for sampling and a
