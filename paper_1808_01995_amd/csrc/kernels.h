@@ -76,8 +76,12 @@ struct StepParams {
     const float4* inj_inc;
 };
 
-// Largest number of injection entries a block can stage in LDS.
-constexpr int kInjCap = 1024;
+// Largest number of injection entries a block can stage in LDS (20 bytes
+// each): 3D blocks span 8 rows and hold many receivers; 2D blocks are one row
+// and small, so that their LDS does not limit residency.
+constexpr int kInjCap3 = 1024;
+constexpr int kInjCap2 = 256;
+inline int inj_cap(int ndim) { return ndim == 3 ? kInjCap3 : kInjCap2; }
 
 // One grid of a batched step launch (see k_step_batch).
 struct BatchJob {

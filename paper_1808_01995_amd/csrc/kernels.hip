@@ -129,8 +129,9 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
     constexpr int JY = NHY > 0 ? (NHY + NT - 1) / NT : 1;
     constexpr int JZ = (NHZ + NT - 1) / NT;
     __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];
-    __shared__ int inj_xl[kInjCap];
-    __shared__ float4 inj_vl[kInjCap];
+    constexpr int ICAP = D3 ? kInjCap3 : kInjCap2;
+    __shared__ int inj_xl[ICAP];
+    __shared__ float4 inj_vl[ICAP];
 
     const int r = xcd_remap(bidx, p.nblocks);
     if (r >= p.nblocks) return;
@@ -392,8 +393,11 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
     }
 }
 
+// Orders up to 8 in 3D keep at least 3 waves per SIMD (12 per CU, the
+// residency the chunk planner assumes; VGPRs capped at 168). Higher orders
+// would spill under that cap and run at 2.
 template <bool D3, int M, int BZ, int BY, int PF, int MODE>
-__global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
+__global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step(const StepParams p) {
     step_body<D3, M, BZ, BY, PF, MODE>(p, (int)blockIdx.x);
 }
 
@@ -404,7 +408,7 @@ __global__ void __launch_bounds__(BZ * BY) k_step(const StepParams p) {
 // its step n0 + k, alternating its two fields, with this step's injection and
 // sampling rows.
 template <bool D3, int M, int BZ, int BY, int PF>
-__global__ void __launch_bounds__(BZ * BY) k_step_batch(const BatchJob* __restrict__ jobs, int njobs,
+__global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(const BatchJob* __restrict__ jobs, int njobs,
                                                         int k) {
     int lo = 0, hi = njobs - 1;
     const int b = (int)blockIdx.x;

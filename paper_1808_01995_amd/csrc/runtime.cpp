@@ -394,7 +394,7 @@ wf_status PointSet::fused(const Layout& L, const StepParams& p, const FusedInj**
             }
             thr[(size_t)(b * NT + tid)] = make_int2(t0, ne);
         }
-        if (ne - e_b0 > kInjCap) f->ok = false;
+        if (ne - e_b0 > inj_cap(L.ndim)) f->ok = false;
     }
     blk[(size_t)p.nblocks] = ne;
     f->nentries = ne;
