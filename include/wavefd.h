@@ -308,7 +308,10 @@ typedef struct {
 
 /* Create an engine that may hold at most `hbm_budget_bytes` of device memory
  * for admitted requests and run at most `max_slots` requests at once. It owns
- * its own HIP streams on the current device. */
+ * its own HIP streams on the current device and allocates the budget once, at
+ * creation. A gradient request stores every forward wavefield when they fit in
+ * a quarter of the budget, else keeps revolve checkpoints in that quarter
+ * (results are the same bits either way). */
 wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** out);
 
 /* Queue a request; returns at once with a ticket. The request's device inputs

@@ -12,7 +12,11 @@
 //   arrivals are admitted while others are on the GPU and their steps share
 //   launches. The arithmetic of every grid is independent of the batch.
 // * Other requests (large grids, gradients) run on worker threads, each with
-//   its own non-blocking stream, concurrently with the batch.
+//   its own non-blocking stream, concurrently with the batch. A free worker
+//   takes the admitted request with the earliest expected completion (arrival
+//   time plus its estimated run time alone): short requests pass long ones
+//   that arrived at about the same time, and a long request is passed only
+//   by requests that would finish before it anyway.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -125,12 +129,14 @@ namespace {
 constexpr int64_t kSmallPoints = (int64_t)1 << 24;   // batched if the grid has at most this many nodes
 constexpr int kBatchSteps = 32;                        // steps per batch iteration
 constexpr int kWorkers = 2;                            // threads for large requests and gradients
+constexpr int kGradShare = 2 * kWorkers;               // a gradient's checkpoints take <= budget / kGradShare
 
 struct EJob {
     uint64_t ticket = 0;
     wf_request rq{};
     std::vector<double> src, rec;
     bool small = false;
+    double due = 0.0;       // arrival (s, steady clock) + estimated run time alone
     int64_t foot = 0;       // bytes reserved at admission
     int64_t grad_cap = 0;   // bytes the gradient's checkpoints may use
     wf_status st = WF_OK;
@@ -139,6 +145,18 @@ struct EJob {
     const PointSet* ps_src = nullptr;
     const PointSet* ps_rec = nullptr;
 };
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// run time of a request alone, from its streamed bytes at ~5 TB/s: 16 B per
+// node per update for a forward shot; a gradient adds the residual forward
+// sweep, recomputation and the 28-byte imaging sweep (about 3 forward shots)
+double estimate_seconds(const wf_request* r, int64_t npoints) {
+    const double fwd = 16.0 * (double)npoints * (double)std::max(r->nt - 1, 0) / 5e12;
+    return r->kind == WF_REQ_GRADIENT ? 3.0 * fwd : fwd;
+}
 
 int64_t field_bytes_of(const wf_geom* g) {
     Layout L;
@@ -212,17 +230,21 @@ static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
         j->small = L.npoints <= kSmallPoints;
     } else {
         // record scratch (predicted data, residual, partial sums), both
-        // increment tables, adjoint pair and gradient, and a checkpoint pool of
-        // up to 2*32+3 fields (store-all if it fits)
+        // increment tables, adjoint pair and gradient, and a checkpoint pool:
+        // every forward field if they fit in the gradient's share of the
+        // budget (the workers' gradients together hold at most half of it),
+        // else a revolve pool of that size (the arena is allocated once, so
+        // a larger pool costs no allocation, only fewer recomputed steps)
         const int64_t l = r->nt - 1;
         const int64_t rec_bytes = 2 * (int64_t)r->nt * r->nrec * 4 + ((int64_t)1 << 20);
         const int64_t fixed = model + inc_src + inc_rec + rec_bytes + 3 * fb + tables;
-        int64_t pool = std::min<int64_t>(l + 1, 2 * 32 + 3) * fb;
+        int64_t pool = std::min<int64_t>((l + 1) * fb, std::max<int64_t>(5 * fb, budget / kGradShare));
         if (fixed + pool > budget) pool = 5 * fb;   // one snapshot, the minimum
         j->grad_cap = 3 * fb + pool + rec_bytes + ((int64_t)1 << 20);
         j->foot = fixed + pool;
         j->small = false;
     }
+    j->due = now_s() + estimate_seconds(r, L.npoints);
     if (j->foot > budget)
         return fail(WF_E_BUDGET, "request needs about %lld bytes, the engine budget is %lld",
                     (long long)j->foot, (long long)budget);
@@ -263,8 +285,11 @@ void wf_engine::worker() {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !large_ready.empty(); });
             if (large_ready.empty()) break;   // stop requested and nothing left
-            j = large_ready.front();
-            large_ready.pop_front();
+            auto best = large_ready.begin();
+            for (auto it = large_ready.begin(); it != large_ready.end(); ++it)
+                if ((*it)->due < (*best)->due) best = it;
+            j = *best;
+            large_ready.erase(best);
         }
         run_large(j, s);
         complete(j);

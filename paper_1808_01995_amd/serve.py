@@ -7,10 +7,11 @@ request tensors alive, timestamps arrivals and completions, and reports
 latency percentiles and throughput.
 
 `build_request` turns a request description (dimension, grid size, space
-order, steps, kind, seed) into device tensors: a smooth random velocity model,
-a 10 Hz Ricker source at the centre at 20 m depth, receivers at 20 m depth
-(a line in 2D, 64 x 64 in 3D); gradient requests carry observed data modelled
-on a model perturbed by a few percent.
+order, steps, kind, seed) into device tensors: a smooth random velocity model
+(generated on the device: the mix reaches 384^3), a 10 Hz Ricker source at the
+centre at 20 m depth, receivers at 20 m depth (a line in 2D, 64 x 64 in 3D);
+gradient requests carry observed data modelled on a model perturbed by a few
+percent.
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import numpy as np
 import torch
 
 from . import _abi
-from .propagator import Propagator, slowness_sq
+from .propagator import Propagator, pad_replicate
 
 
 @dataclasses.dataclass
@@ -61,10 +62,12 @@ class Request:
 def build_request(spec: Dict, device="cuda", vmin: float = 1.5, vmax: float = 4.5,
                   h: float = 10.0, nbl: int = 40, f0_hz: float = 10.0) -> Request:
     """Device tensors for one serving request (see module docstring)."""
-    from synthetic import grid_receivers, line_receivers, ricker, smooth_random_velocity
+    from synthetic import grid_receivers, line_receivers, ricker, smooth_random_velocity_device
     nd, n, so, steps = spec["ndim"], spec["n"], spec["space_order"], spec["steps"]
     shape = (n,) * nd
-    v = smooth_random_velocity(shape, spec["seed"], sigma=max(2.0, n / 32.0), vmin=vmin, vmax=vmax)
+    v = smooth_random_velocity_device(shape, spec["seed"], sigma=max(2.0, n / 32.0), vmin=vmin, vmax=vmax,
+                                      device=device)
+    v_top = float(v.max())
     ext = (n - 1) * h
     if nd == 2:
         src = np.array([[ext / 2, 20.0]])
@@ -72,26 +75,46 @@ def build_request(spec: Dict, device="cuda", vmin: float = 1.5, vmax: float = 4.
     else:
         src = np.array([[ext / 2, ext / 2, 20.0]])
         rec = grid_receivers(64, 64, ext, ext, 20.0)
-    geom = _abi.make_geom(shape, (h,) * nd, nbl, so, float(v.max()))
-    m = slowness_sq(v, nbl, device)
+    geom = _abi.make_geom(shape, (h,) * nd, nbl, so, v_top)
+    m = pad_replicate(1.0 / (v * v), nbl).float().contiguous()
     nt = steps + 1
-    dt = 0.5 * _abi.wf_critical_dt(geom, float(v.max()) * 1.06)
+    dt = 0.5 * _abi.wf_critical_dt(geom, v_top * 1.06)
     wav = torch.from_numpy(ricker(nt, dt, f0_hz)[:, None].astype(np.float32)).to(device)
     rec_out = torch.empty((nt, rec.shape[0]), dtype=torch.float32, device=device)
     kind = _abi.WF_REQ_FORWARD if spec["kind"] == "forward" else _abi.WF_REQ_GRADIENT
     r = Request(kind, geom, m, dt, nt, src, wav, rec, rec_out, tag=dict(spec))
     if kind == _abi.WF_REQ_GRADIENT:
         # observed data from the model perturbed by `perturb` (smoothly)
-        pattern = smooth_random_velocity(shape, spec["seed"] + 7, sigma=max(2.0, n / 16.0),
-                                         vmin=-1.0, vmax=1.0)
+        pattern = smooth_random_velocity_device(shape, spec["seed"] + 7, sigma=max(2.0, n / 16.0),
+                                                vmin=-1.0, vmax=1.0, device=device)
         v_true = v * (1.0 + spec.get("perturb", 0.05) * pattern)
-        prop = Propagator(v_true, spacing=(h,) * nd, nbl=nbl, space_order=so, c_ref=float(v.max()))
+        m_true = pad_replicate(1.0 / (v_true * v_true), nbl).float().contiguous()
+        del pattern, v_true
+        prop = Propagator(m=m_true, shape=shape, spacing=(h,) * nd, nbl=nbl, space_order=so, c_ref=v_top)
         r.d_obs = prop.forward(dt, nt, src, wav, rec)
         torch.cuda.synchronize()
         prop.close()
+        del m_true
         r.grad_out = torch.empty(m.shape, dtype=torch.float32, device=device)
         r._misfit_buf = ctypes.c_double(0.0)
     return r
+
+
+# the engine gives a gradient request budget / GRADIENT_SHARE bytes of
+# checkpoint memory: every forward field if they fit, else a revolve pool
+GRADIENT_SHARE = 4
+
+
+def gradient_memory(budget: int, npoints: int, nt: int, nrec: int):
+    """(n_checkpoints, hbm_budget_bytes) for the plain propagator's gradient
+    call that give it the checkpoint memory the engine gives a gradient
+    request under `budget`, so that both run the same schedule (up to the
+    field padding, estimated here as 10 %)."""
+    fb = npoints * 4
+    share = budget // GRADIENT_SHARE
+    if int(1.1 * nt * fb) <= share:
+        return -1, 0
+    return 0, max(5 * fb, share) + 3 * fb + 2 * nt * nrec * 4 + (1 << 20)
 
 
 class Server:
@@ -192,27 +215,51 @@ def run_stream(server: Server, requests: List[Request], arrivals: Optional[List[
             "mean_ms": float(lat.mean() * 1e3), "failed": len(bad)}
 
 
-def run_one_shot_baseline(requests: List[Request]) -> Dict:
+def run_one_shot_baseline(requests: List[Request], budget: Optional[int] = None,
+                          time_reuse: bool = False) -> Dict:
     """The plain propagator, one request at a time (model created per request,
     one kernel launch per time step; gradients by the two-solve multi-shot
-    call with one shot, the same work the engine does): the reference
-    throughput mu_0."""
+    call with one shot and the checkpoint memory an engine with `budget`
+    gives them, so the same work the engine does): the reference throughput
+    mu_0. Each model allocates its fields and gradient workspace with
+    hipMalloc, which the engine's arena avoids; with `time_reuse` every
+    gradient runs a second time on the same model (its workspace reused) and
+    `seconds_without_workspace_allocation` charges the second run instead of
+    the first."""
+    if budget is None:
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(0.9 * free)
     t0 = time.perf_counter()
     outs = []
+    alloc = 0.0
+    extra = 0.0   # second gradient runs: not part of the one-shot time
     for r in requests:
         nd = r.geom.ndim
         shape = tuple(r.geom.n[a] for a in range(nd))
         prop = Propagator(m=r.m, shape=shape, spacing=tuple(r.geom.h[a] for a in range(nd)),
                           nbl=r.geom.nbl, space_order=r.geom.space_order, c_ref=r.geom.c_ref)
         if r.kind == _abi.WF_REQ_GRADIENT:
-            _, g, (d,) = prop.fwi_gradient(r.dt, r.nt, [(r.src_xyz, r.src_wav, r.rec_xyz, r.d_obs)],
+            nck, cap = gradient_memory(budget, prop.npoints, r.nt, r.rec_xyz.shape[0])
+            shot = [(r.src_xyz, r.src_wav, r.rec_xyz, r.d_obs)]
+            ta = time.perf_counter()
+            _, g, (d,) = prop.fwi_gradient(r.dt, r.nt, shot, n_checkpoints=nck, hbm_budget_bytes=cap,
                                            return_pred=True)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            if time_reuse:
+                prop.fwi_gradient(r.dt, r.nt, shot, n_checkpoints=nck, hbm_budget_bytes=cap)
+                torch.cuda.synchronize()
+                tc = time.perf_counter()
+                alloc += (tb - ta) - (tc - tb)
+                extra += tc - tb
             outs.append((d, g))
         else:
             d = prop.forward(r.dt, r.nt, r.src_xyz, r.src_wav, r.rec_xyz)
             outs.append((d, None))
         torch.cuda.synchronize()
         prop.close()
-    t1 = time.perf_counter()
-    return {"requests": len(requests), "seconds": t1 - t0, "shots_per_s": len(requests) / (t1 - t0),
-            "outputs": outs}
+    el = time.perf_counter() - t0 - extra
+    out = {"requests": len(requests), "seconds": el, "shots_per_s": len(requests) / el, "outputs": outs}
+    if time_reuse:
+        out["seconds_without_workspace_allocation"] = el - alloc
+    return out

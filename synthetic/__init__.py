@@ -30,6 +30,7 @@ __all__ = [
     "config",
     "CONFIG_NAMES",
     "smooth_random_velocity",
+    "smooth_random_velocity_device",
     "two_layer_velocity",
     "gaussian_anomaly_velocity",
     "line_receivers",
@@ -66,6 +67,39 @@ def smooth_random_velocity(shape, seed: int, sigma: float = 8.0,
     if hi <= lo:
         return np.full(shape, 0.5 * (vmin + vmax))
     return vmin + (vmax - vmin) * (s - lo) / (hi - lo)
+
+
+def smooth_random_velocity_device(shape, seed: int, sigma: float = 8.0, vmin: float = 1.5,
+                                  vmax: float = 4.5, device="cuda"):
+    """The recipe of smooth_random_velocity generated on a torch device, for
+    workloads whose host-side filtering would take minutes (the serving mix
+    reaches 384^3): N(0,1) noise from a device generator seeded with `seed`
+    (a different random stream from the host recipe), smoothed by the same
+    separable Gaussian truncated at 4 sigma with half-sample-symmetric edges
+    (scipy's mode 'reflect'), min-max rescaled to [vmin, vmax] km/s.
+    Returns a float64 tensor on `device`."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    x = torch.randn(tuple(int(n) for n in shape), generator=gen, device=device, dtype=torch.float32)
+    r = int(4.0 * float(sigma) + 0.5)
+    taps = np.exp(-0.5 * (np.arange(-r, r + 1) / float(sigma)) ** 2)
+    taps /= taps.sum()
+    for ax in range(x.dim()):
+        n = x.shape[ax]
+        k = np.arange(-r, n + r) % (2 * n)
+        k = np.where(k >= n, 2 * n - 1 - k, k)
+        xp = x.index_select(ax, torch.from_numpy(k).to(device))
+        y = torch.zeros_like(x)
+        for t in range(2 * r + 1):
+            y.add_(xp.narrow(ax, t, n), alpha=float(taps[t]))
+        x = y
+    x = x.double()
+    lo, hi = float(x.min()), float(x.max())
+    if hi <= lo:
+        return torch.full_like(x, 0.5 * (vmin + vmax))
+    return vmin + (vmax - vmin) * (x - lo) / (hi - lo)
 
 
 def two_layer_velocity(shape, v_top: float = 1.5, v_bottom: float = 2.5,
