@@ -213,6 +213,7 @@ def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
     from synthetic import config, ricker
     res = []
     v = None
+    stream = None
     for so in orders:
         c = config("c3_sweep", space_order=so, steps=steps)
         if v is None:
@@ -229,12 +230,15 @@ def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
         ms, n = _abi.wf_profile_read(0, reset=True)
         us = ms / max(n, 1) * 1e3
         gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
+        if stream is None:
+            stream = _abi.wf_stream_bandwidth(prop.npoints, 10)
         res.append({"space_order": so, "dt_ms": round(dt, 4), "gpts": round(prop.npoints * c.steps / el / 1e9, 1),
-                    "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs), "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3)})
+                    "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs), "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3),
+                    "frac_of_stream": round(gbs / stream, 3)})
         prop.close()
         log("c3 so%d: %s" % (so, res[-1]))
     return {"workload": "592^3 computational (512^3 + 40-node layer), two-layer 1.5/2.5 km/s, %d updates" % steps,
-            "orders": res}
+            "stream_GBs": round(stream, 1), "orders": res}
 
 
 def gradient_c4(torch, steps=2000, snaps=(-1, 50, 20, -2)):
@@ -547,6 +551,8 @@ def main():
     _abi.wf_graph_enable(False)
 
     copy_gbs = copy_bandwidth(torch)
+    # the same 16 bytes per node as a plain stream over arrays of the grid's size
+    stream_gbs = _abi.wf_stream_bandwidth(npts, 20)
 
     ms_per_shot = el / args.steps * 1e3
     updates = npts * c.steps
@@ -588,7 +594,12 @@ def main():
                      "launches_in_timed_region": args.steps * c.steps,
                      "algorithmic_bytes_per_launch": BYTES_PER_POINT * npts,
                      "measured_copy_GBs": round(copy_gbs, 1),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4),
+                     "measured_stream_GBs": round(stream_gbs, 1),
+                     "frac_of_measured_stream": round(achieved / stream_gbs, 4),
+                     "stream_note": "wf_stream_bandwidth: 3 float reads + 1 float write per node "
+                                    "(the step kernel's algorithmic bytes) over %d-float arrays, no stencil"
+                                    % npts},
     }
 
     if args.extras:

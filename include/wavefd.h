@@ -282,6 +282,17 @@ wf_status wf_profile_enable(int on);
  * clears the record of every kind. */
 wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int reset);
 
+/* Bandwidth reference for the roofline (Section "Performance", subsection
+ * "Roofline analysis", bounds its kernels by a measured stream bandwidth):
+ * reads three device arrays of n_floats floats and writes a fourth - the
+ * step kernel's 16 bytes per node with no stencil, halo or reuse - one float4
+ * per thread with non-temporal loads and stores, once to warm up and then
+ * `reps` times on a stream of its own, and stores in *gbs_out the rate in
+ * GB/s (16 n_floats bytes per pass over the mean pass time). Allocates and
+ * frees 16 n_floats bytes of device memory on the current device; blocks
+ * until done. n_floats in [1024, 2^34], reps >= 1, else WF_E_ARG. */
+wf_status wf_stream_bandwidth(int64_t n_floats, int reps, double* gbs_out);
+
 /* ------------------------------------------------------------------------ */
 /* Serving engine: continuous batching of forward and gradient requests.     */
 /* ------------------------------------------------------------------------ */

@@ -111,6 +111,7 @@ def _load():
         "wf_revolve_forward_steps": (I64, [I64, I]),
         "wf_profile_enable": (I, [I]),
         "wf_profile_read": (I, [I, P, P, I]),
+        "wf_stream_bandwidth": (I, [I64, I, P]),
         "wf_engine_create": (I, [I64, I, P]),
         "wf_engine_submit": (I, [P, ctypes.POINTER(wf_request), P]),
         "wf_engine_poll": (I, [P, P, P, I, P, I]),
@@ -132,6 +133,7 @@ EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf
            "wf_model_trim",
            "wf_model_destroy", "wf_forward", "wf_adjoint",
            "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
+           "wf_stream_bandwidth",
            "wf_engine_create", "wf_engine_submit",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
 
@@ -324,6 +326,15 @@ def wf_profile_read(kind: int, reset: bool = False):
     n = ctypes.c_int64()
     _check(lib.wf_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def wf_stream_bandwidth(n_floats: int, reps: int = 20) -> float:
+    """GB/s of a plain 3-read + 1-write float4 stream over n_floats-float
+    arrays (the step kernel's bytes per node, no stencil): the roofline's
+    measured reference."""
+    g = ctypes.c_double()
+    _check(lib.wf_stream_bandwidth(int(n_floats), int(reps), ctypes.byref(g)))
+    return g.value
 
 
 def wf_engine_create(hbm_budget_bytes: int, max_slots: int):

@@ -102,3 +102,14 @@ def test_revolve_counts_are_optimal():
     assert _abi.wf_revolve_forward_steps(2000, 2000) == 1999
     assert _abi.wf_revolve_forward_steps(0, 3) == -1
     assert _abi.wf_revolve_forward_steps(5, 0) == -1
+
+
+def test_stream_bandwidth_argument_checks():
+    """Argument errors are reported before any device work."""
+    import ctypes
+    from paper_1808_01995_amd import WaveFDError, _abi
+    for n, reps in ((10, 5), (1 << 35, 5), (4096, 0)):
+        with pytest.raises(WaveFDError) as e:
+            _abi.wf_stream_bandwidth(n, reps)
+        assert e.value.status == _abi.WF_E_ARG
+    assert _abi.lib.wf_stream_bandwidth(4096, 1, None) == _abi.WF_E_ARG
