@@ -1,0 +1,114 @@
+"""Parity at the full sizes of the sweep and gradient workloads, in the
+launch configuration the benchmark times.
+
+* 592^3 computational (512^3 + 40-node layer), two layers 1.5 / 2.5 km/s,
+  every space order 4 / 8 / 12 / 16: 60 updates of a 40 Hz Ricker delayed by
+  10 ms at the sweep's source, recorded on a window of nodes around it,
+  against the FP64 oracle's record stored by tests/golden/make_golden.py
+  (rel. L2 <= 1e-4).
+* 280^3 computational, order 8, 2000 updates: the records of the true and
+  the initial model at every 10th receiver in x and y against the stored
+  oracle records (<= 1e-4); the gradient of the initial model's misfit with
+  every forward field stored and with revolve checkpointing at 50 and 20
+  snapshots (bitwise equal); its transpose pair with Born modelling at full
+  size, <J dm, r> = <dm, J^T r> with dm = m_true - m_initial, held to the
+  gradient's bar (1e-3 relative) rather than the forward/adjoint dot test's
+  1e-4: both sides are 2000-update FP32 computations (the gradient an FP32
+  sum of 2000 imaging terms per node), and <dm, J^T r> sums terms of both
+  signs, which multiplies their relative rounding by the printed
+  cancellation ratio sum |dm g| / |sum dm g| (measured: 1.4e-4 with a ratio
+  of 15, i.e. about 1e-5 of rounding per term, the size of the records'
+  8e-6 error against the oracle; the same pair on the small grids of the
+  Born tests holds to 1e-4).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from _harness import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    path = os.path.join(GOLD, name)
+    if not os.path.exists(path):
+        pytest.skip("stored oracle record %s not generated" % name)
+    return np.load(path)
+
+
+@pytest.mark.parametrize("k", [4, 8, 12, 16])
+def test_c3_full_size_window_against_oracle(k):
+    import oracle
+    from paper_1808_01995_amd import Propagator
+    from synthetic import config, ricker
+    gold = _load("c3_window_records.npz")
+    c = config("c3_sweep")
+    v = c.velocity()
+    vmax = float(v.max())
+    assert vmax == float(gold["vmax"])
+    m32 = (1.0 / oracle.pad_edge(v, c.nbl) ** 2).astype(np.float32)
+    del v
+    prop = Propagator(m=torch.from_numpy(m32).cuda(), shape=c.shape, spacing=c.spacing, nbl=c.nbl,
+                      space_order=k, c_ref=vmax)
+    del m32
+    dt = float(gold["dt_so%d" % k])
+    assert abs(dt - 0.5 * prop.critical_dt(vmax)) <= 1e-12 * dt
+    nt = int(gold["nt"])
+    q = torch.from_numpy(ricker(nt, dt, 40.0, t0=10.0)[:, None].astype(np.float32)).cuda()
+    d = prop.forward(dt, nt, c.src, q, gold["rec_xyz"]).cpu().numpy()
+    prop.close()
+    ref = gold["record_so%d" % k]
+    err = rel_l2(d[::4], ref)
+    print("592^3 order %d: window record rel L2 %.3g (max |u| %.3g)" % (k, err, np.abs(ref).max()))
+    assert np.abs(ref).max() > 1.0
+    assert err <= 1e-4
+
+
+def test_c4_full_size_records_gradient_and_born():
+    import oracle
+    from paper_1808_01995_amd import Propagator
+    from synthetic import config, ricker
+    gold = _load("c4_records_sampled.npz")
+    c = config("c4_gradient")
+    sel = gold["receiver_index"]
+    dt = float(gold["dt"])
+    nt = int(gold["nt"])
+    assert nt == c.nt
+    q = torch.from_numpy(ricker(nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    props, recs = {}, {}
+    for name, v in (("true", c.velocity()), ("initial", np.full(c.shape, 2.0))):
+        m32 = (1.0 / oracle.pad_edge(v, c.nbl) ** 2).astype(np.float32)
+        p = Propagator(m=torch.from_numpy(m32).cuda(), shape=c.shape, spacing=c.spacing, nbl=c.nbl,
+                       space_order=8, c_ref=2.5)
+        assert abs(dt - 0.5 * p.critical_dt(2.5)) <= 1e-12 * dt
+        d = p.forward(dt, nt, c.src, q, c.rec)
+        err = rel_l2(d.cpu().numpy()[::4][:, sel], gold["record_" + name])
+        print("280^3 %s model: sampled record rel L2 %.3g" % (name, err))
+        assert err <= 1e-4
+        props[name], recs[name] = p, d
+    p0 = props["initial"]
+    r = (recs["initial"] - recs["true"]).contiguous()
+    g_all = p0.gradient(dt, nt, c.src, q, c.rec, r, n_checkpoints=-1)
+    for s in (50, 20):
+        g = p0.gradient(dt, nt, c.src, q, c.rec, r, n_checkpoints=s)
+        assert torch.equal(g, g_all), s
+        del g
+    p0.trim()
+    dm = (props["true"].m - p0.m).contiguous()
+    dd = p0.born(dt, nt, c.src, q, dm, c.rec)
+    torch.cuda.synchronize()
+    lhs = float((dd.double() * r.double()).sum())
+    rhs = float((dm.double() * g_all.double()).sum())
+    rel = abs(lhs - rhs) / abs(lhs)
+    canc_l = float((dd.double() * r.double()).abs().sum()) / abs(lhs)
+    canc_r = float((dm.double() * g_all.double()).abs().sum()) / abs(rhs)
+    print("280^3 Born/gradient dot test: %.9e %.9e rel %.2e (cancellation %.1f / %.1f)"
+          % (lhs, rhs, rel, canc_l, canc_r))
+    assert rel <= 1e-3
+    for p in props.values():
+        p.close()
