@@ -112,3 +112,39 @@ def test_c4_full_size_records_gradient_and_born():
     assert rel <= 1e-3
     for p in props.values():
         p.close()
+
+
+def test_grid_beyond_2_31_nodes_matches_small_grid():
+    """64-bit addressing: a 1300^3 grid (2.2e9 nodes per field, 8.9 GB, node
+    offsets past 2^31 beyond x = 1259) with no damping layer, constant
+    2 km/s, a source at x = 1250.5 cells, 48.5 cells from the far x face,
+    and 27 receivers around it; 20 updates of order 8 reach 80 cells. The
+    same source and receivers 48.5 cells from the far x face of a 200^3 grid
+    see the same discrete problem (every other face is out of reach in both):
+    the records must be bitwise equal."""
+    from paper_1808_01995_amd import Propagator
+    from synthetic import ricker
+    h = 10.0
+    k, nsteps = 8, 20
+    recs = {}
+    for n_big in (1300, 200):
+        shape = (n_big, 200 if n_big == 200 else 1300, 200 if n_big == 200 else 1300)
+        cx = n_big - 49.5
+        cyz = 100.5 if n_big == 200 else 650.5
+        m = torch.full(shape, 0.25, dtype=torch.float32, device="cuda")
+        prop = Propagator(m=m, shape=shape, spacing=(h, h, h), nbl=0, space_order=k, c_ref=2.0)
+        dt = 0.5 * prop.critical_dt(2.0)
+        nt = nsteps + 1
+        q = torch.from_numpy(ricker(nt, dt, 40.0, t0=5.0)[:, None].astype(np.float32)).cuda()
+        src = np.array([[cx * h, cyz * h, cyz * h]])
+        off = np.array([-6.25, 0.25, 6.25]) * h
+        rec = np.array([[cx * h + a, cyz * h + b, cyz * h + c] for a in off for b in off for c in off])
+        recs[n_big] = prop.forward(dt, nt, src, q, rec).cpu()
+        prop.close()
+        del m
+        torch.cuda.empty_cache()
+    big, small = recs[1300], recs[200]
+    print("1300^3 vs 200^3: max |d| %.3e, max diff %.3e" % (float(small.abs().max()),
+                                                              float((big - small).abs().max())))
+    assert float(small.abs().max()) > 0.0
+    assert torch.equal(big, small)
