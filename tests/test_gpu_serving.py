@@ -139,3 +139,36 @@ def test_invalid_request_rejected_without_disturbing():
     srv.drain()
     assert all(r.status == 0 for r in reqs[:2])
     srv.close()
+
+
+def test_gradient_checkpoints_in_a_quarter_of_the_budget():
+    """A gradient request whose forward fields do not fit in a quarter of the
+    engine budget runs with revolve checkpoints in that quarter; the
+    one-shot baseline's memory rule gives the plain propagator the same
+    schedule. Both gradients and misfits equal the store-all gradient of the
+    plain propagator bitwise (the result does not depend on the schedule)."""
+    from paper_1808_01995_amd import Propagator, _abi
+    from paper_1808_01995_amd.serve import Server, gradient_memory, run_stream
+    spec = {"ndim": 2, "n": 200, "space_order": 8, "steps": 1000, "kind": "gradient", "seed": 61,
+            "perturb": 0.05}
+    r = _build([spec], nbl=20)[0]
+    budget = 256 << 20
+    nd = r.geom.ndim
+    shape = tuple(r.geom.n[a] for a in range(nd))
+    prop = Propagator(m=r.m, shape=shape, spacing=tuple(r.geom.h[a] for a in range(nd)), nbl=r.geom.nbl,
+                      space_order=r.geom.space_order, c_ref=r.geom.c_ref)
+    fields = r.nt * prop.npoints * 4
+    assert fields > budget // 4 and fields < budget   # store-all fits the budget, not the share
+    shot = [(r.src_xyz, r.src_wav, r.rec_xyz, r.d_obs)]
+    phi_all, g_all = prop.fwi_gradient(r.dt, r.nt, shot, n_checkpoints=-1)
+    nck, cap = gradient_memory(budget, prop.npoints, r.nt, r.rec_xyz.shape[0])
+    assert nck == 0 and cap < fields
+    phi_b, g_b = prop.fwi_gradient(r.dt, r.nt, shot, n_checkpoints=nck, hbm_budget_bytes=cap)
+    assert torch.equal(g_b, g_all) and phi_b == phi_all
+    prop.close()
+    srv = Server(hbm_budget_bytes=budget, max_slots=4)
+    run_stream(srv, [r])
+    srv.close()
+    assert r.status == 0
+    assert torch.equal(r.grad_out, g_all)
+    assert r.misfit == phi_all
