@@ -19,7 +19,8 @@ launch configuration the benchmark times.
   cancellation ratio sum |dm g| / |sum dm g| (measured: 1.4e-4 with a ratio
   of 15, i.e. about 1e-5 of rounding per term, the size of the records'
   8e-6 error against the oracle; the same pair on the small grids of the
-  Born tests holds to 1e-4).
+  Born tests holds to 1e-4); and a Taylor test of that gradient along dm
+  (slopes 1 and 2).
 """
 import os
 
@@ -110,6 +111,25 @@ def test_c4_full_size_records_gradient_and_born():
     print("280^3 Born/gradient dot test: %.9e %.9e rel %.2e (cancellation %.1f / %.1f)"
           % (lhs, rhs, rel, canc_l, canc_r))
     assert rel <= 1e-3
+    # Taylor test at full size along dm: |phi(m0 + h dm) - phi(m0)| is first
+    # order in h and |... - h <g, dm>| second order, over h = 1/2 .. 1/32
+    d_obs = recs["true"]
+    f0 = 0.5 * float((r.double() ** 2).sum())
+    gdm = float((g_all.double() * dm.double()).sum())
+    m0 = p0.m.clone()
+    hs = 2.0 ** -np.arange(1, 6)
+    e0, e1 = [], []
+    for hh in hs:
+        p0.set_m((m0 + hh * dm).contiguous())
+        d = p0.forward(dt, nt, c.src, q, c.rec)
+        f = 0.5 * float(((d - d_obs).double() ** 2).sum())
+        e0.append(abs(f - f0))
+        e1.append(abs(f - f0 - hh * gdm))
+    p0.set_m(m0)
+    s0 = np.polyfit(np.log(hs), np.log(e0), 1)[0]
+    s1 = np.polyfit(np.log(hs), np.log(e1), 1)[0]
+    print("280^3 Taylor slopes %.3f %.3f" % (s0, s1))
+    assert 0.85 < s0 < 1.2 and 1.7 < s1 < 2.4
     for p in props.values():
         p.close()
 
