@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -89,10 +90,34 @@ def cpu_baseline(c, v, dt, sample_steps: int):
     oracle.forward(g, m, eta, dt, nt, src, q, rec)
     el = time.perf_counter() - t
     cores = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
-    return {"value": m.size * sample_steps / el / 1e9, "unit": "GPts/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "FP64 oracle, %d of %d updates of the same %s-point shot (%.1f s)"
-                      % (sample_steps, c.steps, "x".join(map(str, m.shape)), el)}
+    out = {"value": m.size * sample_steps / el / 1e9, "unit": "GPts/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "FP64 oracle, %d of %d updates of the same %s-point shot (%.1f s)"
+                     % (sample_steps, c.steps, "x".join(map(str, m.shape)), el)}
+    if sample_steps >= 10:
+        # the same oracle on one core (a child process with one OpenMP thread)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-core", "8"],
+                           env=env, capture_output=True, text=True, timeout=300)
+        lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+        if r.returncode == 0 and lines:
+            one = json.loads(lines[-1])
+            out["value_one_core"] = one["value"]
+            out["sample_one_core"] = one["sample"]
+    return out
+
+
+def oracle_one_core(steps: int):
+    """Child of cpu_baseline: the oracle with one OpenMP thread on the first
+    `steps` updates of the 3D order-8 shot (no GPU use)."""
+    from synthetic import config
+    import oracle
+    c = config("c2_3d_so8")
+    v = c.velocity()
+    dt = c.dt_factor * oracle.critical_dt(3, c.spacing, c.space_order, float(v.max()))
+    r = cpu_baseline(c, v, dt, min(steps, 9))
+    print(json.dumps({"value": r["value"], "sample": r["sample"].replace("FP64 oracle", "FP64 oracle, 1 thread")}),
+          flush=True)
 
 
 def _timed(torch, fn, reps=1):
@@ -488,7 +513,11 @@ def main():
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the gradient and Born kernels for a profiler: 280^3 order 8, "
                          "400 updates, two store-all gradients and two Born modellings")
+    ap.add_argument("--oracle-one-core", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_one_core:
+        oracle_one_core(args.oracle_one_core)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
