@@ -131,6 +131,19 @@ int64_t wf_model_bytes(const wf_model* model);
  * allocates it again. Synchronises the model's device work. */
 wf_status wf_model_trim(wf_model* model);
 
+/* Validation aid. Outside the computational grid the wavefield is zero
+ * (Section "Boundary conditions": the zero Dirichlet condition beyond the
+ * damping layer); the library stores that outside as ghost planes before and
+ * after the x range and as row padding beyond nz of every pitched field, which
+ * the stencil reads and no kernel may write. Stores in *count the number of
+ * nonzero values (NaN included) found there in the model's kappa and
+ * wavefield buffers and, while it is marked clean, in every field slot of its
+ * gradient workspace (after a boundary-reconstruction gradient it is not: its
+ * slabs reuse those slots until the next gradient call clears them). 0 after
+ * any correct sequence of calls. Waits for the model's device work; blocks;
+ * allocates 8 bytes of device memory. NULL arguments: WF_E_ARG. */
+wf_status wf_model_ghost_nonzero(wf_model* model, int64_t* count);
+
 /* Time loops of wf_forward / wf_adjoint on this model that were launched as a
  * captured HIP graph. While capture is enabled (wf_graph_enable), a call runs
  * eagerly the first time its signature (dt, nt, point coordinates, every

@@ -105,6 +105,13 @@ wf_status wf_model_trim(wf_model* model) {
     ABI_GUARD_END
 }
 
+wf_status wf_model_ghost_nonzero(wf_model* model, int64_t* count) {
+    ABI_GUARD_BEGIN
+    if (!model || !count) return fail(WF_E_ARG, "NULL argument");
+    return count_ghost_nonzero(*as_model(model), count);
+    ABI_GUARD_END
+}
+
 wf_status wf_graph_enable(int on) {
     set_graphs_enabled(on != 0);
     return WF_OK;

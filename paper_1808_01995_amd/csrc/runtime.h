@@ -261,6 +261,11 @@ wf_status batch_forward_finish(BatchFwd& b, hipStream_t s);
 // Free device memory the current thread may allocate (its arena, if any).
 int64_t device_free_bytes();
 
+// Nonzero values (NaN included) in the ghost planes and row padding of the
+// model's kappa and wavefield buffers and, while it is marked clean, of every
+// field slot of its gradient workspace. Synchronous.
+wf_status count_ghost_nonzero(const Model& md, int64_t* out);
+
 // Revolve schedule (revolve.cpp).
 int64_t revolve_cost(int64_t steps, int snaps);
 struct RevolveAction {

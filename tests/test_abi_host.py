@@ -113,3 +113,8 @@ def test_stream_bandwidth_argument_checks():
             _abi.wf_stream_bandwidth(n, reps)
         assert e.value.status == _abi.WF_E_ARG
     assert _abi.lib.wf_stream_bandwidth(4096, 1, None) == _abi.WF_E_ARG
+
+
+def test_ghost_check_argument_checks():
+    from paper_1808_01995_amd import _abi
+    assert _abi.lib.wf_model_ghost_nonzero(None, None) == _abi.WF_E_ARG

@@ -244,3 +244,35 @@ def test_c2_full_size_against_stored_oracle_record():
     print("C2 full-size sampled record rel L2 = %.3g" % err)
     assert err <= 1e-4
     prop.close()
+
+
+@pytest.mark.parametrize("shape,k", [((37, 29, 41), 16), ((33, 27, 130), 8), ((57, 49), 8)])
+def test_ghost_region_stays_zero(shape, k):
+    """No kernel writes outside the grid: after forward (with saved fields),
+    adjoint, gradients (store-all, revolve, boundary reconstruction) and Born
+    modelling, the ghost planes and row padding of the model's fields and of
+    its clean gradient workspace still hold only zeros."""
+    from _harness import noise
+    from paper_1808_01995_amd import _abi
+    P = make_problem(shape, 7, k, 40, seed=90 + k, nsrc=3, nrec=37)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    ghosts = lambda: _abi.wf_model_ghost_nonzero(prop.handle)   # noqa: E731
+    assert ghosts() == 0
+    d, u = prop.forward(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, save_every=7)
+    assert ghosts() == 0
+    r = torch.from_numpy(noise(P.nt, P.rec_xyz.shape[0], P.dt, 15.0, 3).astype(np.float32)).cuda()
+    prop.adjoint(P.dt, P.nt, P.rec_xyz, r, P.src_xyz)
+    assert ghosts() == 0
+    g_all = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    assert ghosts() == 0
+    g_rev = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=3)
+    assert ghosts() == 0 and torch.equal(g_rev, g_all)
+    prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-2)
+    assert ghosts() == 0          # its slabs occupy workspace slots: those are not checked
+    prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r, n_checkpoints=-1)
+    assert ghosts() == 0          # cleared again, every slot checked
+    dm = torch.full(prop.comp_shape, 1e-3, device="cuda")
+    prop.born(P.dt, P.nt, P.src_xyz, q, dm, P.rec_xyz)
+    assert ghosts() == 0
+    prop.close()
