@@ -22,7 +22,15 @@ For the gradient workload (200^3 physical, 280^3 computational, order 8,
 model (the observed data) and of the 2 km/s initial model at every 10th
 receiver in x and y (100 traces), every 4th sample.
 
-Usage: python tests/golden/make_golden.py [c2] [c3] [c4]
+For the same gradient workload, the oracle's J^T r of the initial model for
+a seeded band-limited residual r at all 100 x 100 receivers (two-level
+checkpointing), on the plane y = 140 through the source and the anomaly,
+every 2nd node in x and z. (The workload's own residual, the initial minus
+the true model's record, is 7e-5 of the records, so the records' float32
+rounding leaves it a few percent uncertain: a shared residual compares the
+gradient operators themselves.)
+
+Usage: python tests/golden/make_golden.py [c2] [c3] [c4] [c4g]
 """
 import os
 import sys
@@ -118,6 +126,31 @@ def c4_records(path):
     np.savez_compressed(path, **out)
 
 
+C4G_NOISE = {"f0_hz": 10.0, "seed": 44}
+
+
+def c4_gradient_slice(path):
+    """J^T r of the initial model for a seeded band-limited residual r at all
+    100 x 100 receivers (the same float32 values the GPU gets), forward
+    history by the oracle's two-level checkpointing."""
+    from synthetic import band_limited_noise
+    c = config("c4_gradient")
+    dt = 0.5 * oracle.critical_dt(3, c.spacing, 8, 2.5)
+    q64 = ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32).astype(np.float64)
+    m0 = (1.0 / oracle.pad_edge(np.full(c.shape, 2.0), c.nbl) ** 2).astype(np.float32).astype(np.float64)
+    g = oracle.Grid(m0.shape, c.spacing, 8)
+    eta = oracle.damping_eta(c.shape, c.nbl, c.spacing, 2.5)
+    src_p = oracle.sparse_points(c.src, c.spacing, c.nbl, g.shape)
+    rec_p = oracle.sparse_points(c.rec, c.spacing, c.nbl, g.shape)
+    r = band_limited_noise(c.nt, c.rec.shape[0], dt, C4G_NOISE["f0_hz"], C4G_NOISE["seed"])
+    r = r.astype(np.float32).astype(np.float64)
+    t = time.time()
+    grad = oracle.gradient(g, m0, eta, dt, c.nt, src_p, q64, rec_p, r)
+    print("oracle C4 gradient: %.1f s" % (time.time() - t), flush=True)
+    np.savez_compressed(path, gradient=grad[::2, 140, ::2].astype(np.float32), y_index=140, step=2,
+                        noise_f0_hz=C4G_NOISE["f0_hz"], noise_seed=C4G_NOISE["seed"], dt=dt, nt=c.nt)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c2"]
     if "c2" in which:
@@ -126,3 +159,5 @@ if __name__ == "__main__":
         c3_windows(os.path.join(HERE, "c3_window_records.npz"))
     if "c4" in which:
         c4_records(os.path.join(HERE, "c4_records_sampled.npz"))
+    if "c4g" in which:
+        c4_gradient_slice(os.path.join(HERE, "c4_gradient_slice.npz"))
