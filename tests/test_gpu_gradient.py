@@ -198,3 +198,43 @@ def test_boundary_reconstruction_gradient(ndim, nbl):
     assert e_all <= 1e-4
     assert e_ref <= 1e-3
     assert ws < (P.nt // 2) * prop.npoints * 4
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 5])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_short_records(ndim, steps):
+    """Records of 1, 2, 3 and 6 samples: forward, adjoint, the gradient in
+    every checkpointing mode and Born modelling against the oracle (a zero
+    reference must be matched by zeros)."""
+    from _harness import noise
+    shape = (26, 23) if ndim == 2 else (17, 15, 19)
+    P = make_problem(shape, 5, 8, steps, seed=60 + steps + ndim, nrec=21)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    y = noise(P.nt, P.rec_xyz.shape[0], P.dt, 15.0, 9 + steps).astype(np.float32)
+    yt = torch.from_numpy(y).cuda()
+
+    def same(a, ref, tol):
+        ref = np.asarray(ref, dtype=np.float64)
+        if not np.any(ref):
+            return not np.any(a)
+        return rel_l2(a, ref) <= tol
+
+    d = prop.forward(P.dt, P.nt, P.src_xyz, q, P.rec_xyz).cpu().numpy()
+    assert same(d, P.oracle_forward(), 1e-4)
+    x = prop.adjoint(P.dt, P.nt, P.rec_xyz, yt, P.src_xyz).cpu().numpy()
+    assert same(x, P.oracle_adjoint(y.astype(np.float64)), 1e-4)
+    g_ref = P.oracle_gradient(y.astype(np.float64))
+    for nck in (-1, 1, 0):
+        g = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, yt, n_checkpoints=nck).cpu().numpy()
+        assert same(g, g_ref, 1e-3), nck
+    gb = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, yt, n_checkpoints=-2).cpu().numpy()
+    inner = tuple(slice(P.nbl, P.nbl + n) for n in P.shape_phys)
+    assert same(gb[inner], g_ref[inner], 1e-3)
+    import oracle
+    rng = np.random.default_rng(steps)
+    dm = (1e-3 * rng.standard_normal(P.comp_shape)).astype(np.float32)
+    dd = prop.born(P.dt, P.nt, P.src_xyz, q, torch.from_numpy(dm).cuda(), P.rec_xyz).cpu().numpy()
+    dd_ref = oracle.born(P.grid(), P.m64(), P.eta(), P.dt, P.nt, P.pts(P.src_xyz), P.q32.astype(np.float64),
+                         P.pts(P.rec_xyz), dm.astype(np.float64))
+    assert same(dd, dd_ref, 1e-4)
