@@ -172,3 +172,26 @@ def test_gradient_checkpoints_in_a_quarter_of_the_budget():
     assert r.status == 0
     assert torch.equal(r.grad_out, g_all)
     assert r.misfit == phi_all
+
+
+def test_one_sample_requests():
+    """Requests with a one-sample record (no update): the engine completes
+    them with a zero record and, for a gradient, a zero gradient and misfit
+    1/2 |d_obs|^2 (d_obs of one sample is zero too)."""
+    from paper_1808_01995_amd.serve import Server, run_stream
+    specs = [{"ndim": 2, "n": 64, "space_order": 8, "steps": 0, "kind": "forward", "seed": 70},
+             {"ndim": 3, "n": 20, "space_order": 4, "steps": 0, "kind": "forward", "seed": 71},
+             {"ndim": 2, "n": 64, "space_order": 8, "steps": 0, "kind": "gradient", "seed": 72, "perturb": 0.05}]
+    reqs = _build(specs, nbl=6)
+    for r in reqs:
+        r.rec_out.fill_(1.0)
+        if r.grad_out is not None:
+            r.grad_out.fill_(1.0)
+    srv = Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    st = run_stream(srv, reqs)
+    srv.close()
+    assert st["failed"] == 0
+    for r in reqs:
+        assert r.nt == 1 and torch.all(r.rec_out == 0)
+        if r.grad_out is not None:
+            assert torch.all(r.grad_out == 0) and r.misfit == 0.0
