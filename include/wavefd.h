@@ -158,6 +158,19 @@ wf_status wf_model_ghost_nonzero(wf_model* model, int64_t* count);
  * model. */
 int64_t wf_model_graph_launches(const wf_model* model);
 
+/* Process-wide switch of the post-run validation: 1 on, 0 off; off by default,
+ * on at start-up when the environment sets WAVEFD_VALIDATE=1. The paper's
+ * scheme is stable only under its time-step condition (Section "Temporal
+ * discretization"), which every call enforces before any work; non-finite
+ * inputs (a wavelet, residual, dm or m holding Inf or NaN) still propagate.
+ * While on, wf_forward (rec_out, u_save), wf_adjoint (src_out), wf_gradient
+ * (grad_out), wf_born (drec_out, rec_out) and wf_fwi_gradient (grad_out, each
+ * d_pred, the misfit) count the non-finite values of their outputs after the
+ * run, waiting for the stream, and return WF_E_NONFINITE if there are any
+ * (the outputs are written all the same). Requests served by the engine are
+ * not checked. */
+wf_status wf_validate_enable(int on);
+
 /* Process-wide switch for that capture: 1 on, 0 off. Off by default (a
  * replayed kernel node was measured slower than a stream launch on ROCm 7.x),
  * on at start-up when the environment sets WAVEFD_GRAPH=1. Captured loops are

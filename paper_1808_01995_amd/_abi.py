@@ -113,6 +113,7 @@ def _load():
         "wf_profile_read": (I, [I, P, P, I]),
         "wf_stream_bandwidth": (I, [I64, I, P]),
         "wf_model_ghost_nonzero": (I, [P, P]),
+        "wf_validate_enable": (I, [I]),
         "wf_engine_create": (I, [I64, I, P]),
         "wf_engine_submit": (I, [P, ctypes.POINTER(wf_request), P]),
         "wf_engine_poll": (I, [P, P, P, I, P, I]),
@@ -134,7 +135,7 @@ EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf
            "wf_model_trim",
            "wf_model_destroy", "wf_forward", "wf_adjoint",
            "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
-           "wf_stream_bandwidth", "wf_model_ghost_nonzero",
+           "wf_stream_bandwidth", "wf_model_ghost_nonzero", "wf_validate_enable",
            "wf_engine_create", "wf_engine_submit",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
 
@@ -327,6 +328,11 @@ def wf_profile_read(kind: int, reset: bool = False):
     n = ctypes.c_int64()
     _check(lib.wf_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def wf_validate_enable(on):
+    """Post-run checks that every output value is finite (WF_E_NONFINITE)."""
+    _check(lib.wf_validate_enable(1 if on else 0))
 
 
 def wf_model_ghost_nonzero(model) -> int:

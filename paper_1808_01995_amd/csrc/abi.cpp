@@ -112,6 +112,11 @@ wf_status wf_model_ghost_nonzero(wf_model* model, int64_t* count) {
     ABI_GUARD_END
 }
 
+wf_status wf_validate_enable(int on) {
+    set_validation(on != 0);
+    return WF_OK;
+}
+
 wf_status wf_graph_enable(int on) {
     set_graphs_enabled(on != 0);
     return WF_OK;
@@ -144,7 +149,14 @@ wf_status wf_forward(wf_model* model, double dt, int nt, int nsrc, const double*
     const PointSet *src = nullptr, *rec = nullptr;
     if ((st = md.points(nsrc, src_xyz, &src)) != WF_OK) return st;
     if ((st = md.points(nrec, rec_xyz, &rec)) != WF_OK) return st;
-    return run_forward(md, dt, nt, *src, src_wav, *rec, rec_out, u_save, save_every, as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    st = run_forward(md, dt, nt, *src, src_wav, *rec, rec_out, u_save, save_every, s);
+    if (st == WF_OK && validation_enabled()) {
+        st = md.check_finite(rec_out, (int64_t)nt * nrec, "rec_out", s);
+        if (st == WF_OK && u_save)
+            st = md.check_finite(u_save, ((int64_t)(nt - 1) / save_every + 1) * md.L.npoints, "u_save", s);
+    }
+    return st;
     ABI_GUARD_END
 }
 
@@ -162,7 +174,10 @@ wf_status wf_adjoint(wf_model* model, double dt, int nt, int nrec, const double*
     const PointSet *src = nullptr, *rec = nullptr;
     if ((st = md.points(nsrc, src_xyz, &src)) != WF_OK) return st;
     if ((st = md.points(nrec, rec_xyz, &rec)) != WF_OK) return st;
-    return run_adjoint(md, dt, nt, *rec, rec_in, *src, src_out, as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    st = run_adjoint(md, dt, nt, *rec, rec_in, *src, src_out, s);
+    if (st == WF_OK && validation_enabled()) st = md.check_finite(src_out, (int64_t)nt * nsrc, "src_out", s);
+    return st;
     ABI_GUARD_END
 }
 
@@ -183,8 +198,10 @@ wf_status wf_gradient(wf_model* model, double dt, int nt, int nsrc, const double
     const PointSet *src = nullptr, *rec = nullptr;
     if ((st = md.points(nsrc, src_xyz, &src)) != WF_OK) return st;
     if ((st = md.points(nrec, rec_xyz, &rec)) != WF_OK) return st;
-    return run_gradient(md, dt, nt, *src, src_wav, *rec, residual, grad_out, n_checkpoints,
-                        hbm_budget_bytes, as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    st = run_gradient(md, dt, nt, *src, src_wav, *rec, residual, grad_out, n_checkpoints, hbm_budget_bytes, s);
+    if (st == WF_OK && validation_enabled()) st = md.check_finite(grad_out, md.L.npoints, "grad_out", s);
+    return st;
     ABI_GUARD_END
 }
 
@@ -203,7 +220,13 @@ wf_status wf_born(wf_model* model, double dt, int nt, int nsrc, const double* sr
     const PointSet *src = nullptr, *rec = nullptr;
     if ((st = md.points(nsrc, src_xyz, &src)) != WF_OK) return st;
     if ((st = md.points(nrec, rec_xyz, &rec)) != WF_OK) return st;
-    return run_born(md, dt, nt, *src, src_wav, dm, *rec, drec_out, rec_out, as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    st = run_born(md, dt, nt, *src, src_wav, dm, *rec, drec_out, rec_out, s);
+    if (st == WF_OK && validation_enabled()) {
+        st = md.check_finite(drec_out, (int64_t)nt * nrec, "drec_out", s);
+        if (st == WF_OK) st = md.check_finite(rec_out, (int64_t)nt * nrec, "rec_out", s);
+    }
+    return st;
     ABI_GUARD_END
 }
 
@@ -233,8 +256,17 @@ wf_status wf_fwi_gradient(wf_model* model, double dt, int nt, int nshots, const 
         if ((st = md.points(sh.nrec, sh.rec_xyz, &ps)) != WF_OK) return st;
         v[(size_t)i] = FwiShot{sh.nsrc, sh.src_xyz, sh.src_wav, sh.nrec, sh.rec_xyz, sh.d_obs, sh.d_pred};
     }
-    return run_fwi_gradient(md, dt, nt, v, grad_out, misfit_out, n_checkpoints, hbm_budget_bytes,
-                            as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    double phi = 0.0;
+    st = run_fwi_gradient(md, dt, nt, v, grad_out, &phi, n_checkpoints, hbm_budget_bytes, s);
+    if (st == WF_OK && misfit_out) *misfit_out = phi;
+    if (st == WF_OK && validation_enabled()) {
+        st = md.check_finite(grad_out, md.L.npoints, "grad_out", s);
+        for (int i = 0; i < nshots && st == WF_OK; ++i)
+            st = md.check_finite(shots[i].d_pred, (int64_t)nt * shots[i].nrec, "d_pred", s);
+        if (st == WF_OK && !std::isfinite(phi)) st = fail(WF_E_NONFINITE, "the misfit is not finite");
+    }
+    return st;
     ABI_GUARD_END
 }
 

@@ -3,8 +3,8 @@
 #include "runtime.h"
 
 #include <algorithm>
-#include <cfloat>
 #include <atomic>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -494,6 +494,31 @@ wf_status Model::refresh_m(hipStream_t s) {
     return WF_OK;
 }
 
+wf_status Model::check_finite(const float* x, int64_t n, const char* what, hipStream_t s) {
+    if (!x || n <= 0) return WF_OK;
+    unsigned int* cnt = reinterpret_cast<unsigned int*>(d_scratch.ptr);
+    unsigned int bad = 0;
+    WF_TRY_RT(hip_check(hipMemsetAsync(cnt, 0, 4, s), "clear"));
+    WF_TRY_RT(hip_check(launch_count_nonfinite(x, n, cnt, s), "check finite"));
+    WF_TRY_RT(hip_check(hipMemcpyAsync(&bad, cnt, 4, hipMemcpyDeviceToHost, s), "read"));
+    WF_TRY_RT(hip_check(hipStreamSynchronize(s), "sync"));
+    if (bad) return fail(WF_E_NONFINITE, "%s has %u values that are not finite", what, bad);
+    return WF_OK;
+}
+
+namespace {
+std::atomic<int>& validation_switch() {
+    static std::atomic<int> on([] {
+        const char* e = std::getenv("WAVEFD_VALIDATE");
+        return (e && e[0] == '1') ? 1 : 0;
+    }());
+    return on;
+}
+}  // namespace
+
+bool wf::validation_enabled() { return validation_switch().load(std::memory_order_relaxed) != 0; }
+void wf::set_validation(bool on) { validation_switch().store(on ? 1 : 0); }
+
 wf_status Model::update(const float* grad, double alpha, double lo, double hi, float* m_out,
                         hipStream_t s) {
     if (!grad) return fail(WF_E_ARG, "grad is NULL");
@@ -505,13 +530,7 @@ wf_status Model::update(const float* grad, double alpha, double lo, double hi, f
     if (!(flo > 0.0f) || !(fhi >= flo)) return fail(WF_E_ARG, "bounds are not representable in FP32");
     last_stream = s;
     // a non-finite gradient value would be clamped silently: refuse it first
-    unsigned int* cnt = reinterpret_cast<unsigned int*>(d_scratch.ptr);
-    unsigned int bad = 0;
-    WF_TRY_RT(hip_check(hipMemsetAsync(cnt, 0, 4, s), "clear"));
-    WF_TRY_RT(hip_check(launch_count_nonfinite(grad, L.npoints, cnt, s), "check grad"));
-    WF_TRY_RT(hip_check(hipMemcpyAsync(&bad, cnt, 4, hipMemcpyDeviceToHost, s), "read"));
-    WF_TRY_RT(hip_check(hipStreamSynchronize(s), "sync"));
-    if (bad) return fail(WF_E_NONFINITE, "grad has %u values that are not finite", bad);
+    WF_TRY_RT(check_finite(grad, L.npoints, "grad", s));
     WF_TRY_RT(hip_check(launch_update(d_m.f(), grad, (float)alpha, flo, fhi, L.npoints, s), "update"));
     if (m_out)
         WF_TRY_RT(hip_check(hipMemcpyAsync(m_out, d_m.f(), (size_t)L.npoints * 4, hipMemcpyDeviceToDevice, s),

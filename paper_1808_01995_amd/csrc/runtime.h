@@ -163,6 +163,9 @@ struct Model : public wf_model {
     wf::StripGeom strips() const;
     // m <- min(max(m - alpha grad, lo), hi); m_out (optional) receives it
     wf_status update(const float* grad, double alpha, double lo, double hi, float* m_out, hipStream_t s);
+    // WF_E_NONFINITE (naming `what`) if any of the n device floats at x is
+    // not finite; waits for the stream
+    wf_status check_finite(const float* x, int64_t n, const char* what, hipStream_t s);
     wf_status ensure_kap(double dt, hipStream_t s);
     wf_status check_dt(double dt) const;
     double vmax() const;
@@ -192,6 +195,10 @@ struct ProfScope {
 // Time loops (propagate.cpp).
 // Process-wide switch for capturing time loops as HIP graphs.
 void set_graphs_enabled(bool on);
+// post-run checks that every output value is finite (process-wide switch,
+// initially on when WAVEFD_VALIDATE=1)
+bool validation_enabled();
+void set_validation(bool on);
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
                       hipStream_t s);

@@ -118,3 +118,9 @@ def test_stream_bandwidth_argument_checks():
 def test_ghost_check_argument_checks():
     from paper_1808_01995_amd import _abi
     assert _abi.lib.wf_model_ghost_nonzero(None, None) == _abi.WF_E_ARG
+
+
+def test_validation_switch():
+    from paper_1808_01995_amd import _abi
+    assert _abi.lib.wf_validate_enable(1) == _abi.WF_OK
+    assert _abi.lib.wf_validate_enable(0) == _abi.WF_OK

@@ -276,3 +276,40 @@ def test_ghost_region_stays_zero(shape, k):
     prop.born(P.dt, P.nt, P.src_xyz, q, dm, P.rec_xyz)
     assert ghosts() == 0
     prop.close()
+
+
+def test_validation_reports_nonfinite_outputs():
+    """With validation on, a NaN in a wavelet, an Inf in a residual or a NaN
+    in dm makes the call return WF_E_NONFINITE; off, the same calls succeed
+    and their outputs carry the non-finite values; finite inputs pass."""
+    from paper_1808_01995_amd import WaveFDError, _abi
+    P = make_problem((30, 27), 6, 8, 60, seed=12, nrec=25)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    qbad = q.clone()
+    qbad[10, 0] = float("nan")
+    rbad = torch.zeros((P.nt, P.rec_xyz.shape[0]), device="cuda")
+    rbad[30, 3] = float("inf")
+    dmbad = torch.zeros(prop.comp_shape, device="cuda")
+    dmbad[9, 9] = float("nan")
+    try:
+        _abi.wf_validate_enable(True)
+        d = prop.forward(P.dt, P.nt, P.src_xyz, q, P.rec_xyz)   # finite: passes
+        r = (0.1 * d).contiguous()
+        prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, r)
+        prop.adjoint(P.dt, P.nt, P.rec_xyz, r, P.src_xyz)
+        calls = [lambda: prop.forward(P.dt, P.nt, P.src_xyz, qbad, P.rec_xyz),
+                 lambda: prop.adjoint(P.dt, P.nt, P.rec_xyz, rbad, P.src_xyz),
+                 lambda: prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, rbad),
+                 lambda: prop.born(P.dt, P.nt, P.src_xyz, q, dmbad, P.rec_xyz),
+                 lambda: prop.fwi_gradient(P.dt, P.nt, [(P.src_xyz, qbad, P.rec_xyz, d)])]
+        for call in calls:
+            with pytest.raises(WaveFDError) as e:
+                call()
+            assert e.value.status == _abi.WF_E_NONFINITE
+    finally:
+        _abi.wf_validate_enable(False)
+    d_nan = prop.forward(P.dt, P.nt, P.src_xyz, qbad, P.rec_xyz)
+    torch.cuda.synchronize()
+    assert not torch.isfinite(d_nan).all()
+    prop.close()
