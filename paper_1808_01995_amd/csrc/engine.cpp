@@ -30,6 +30,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <new>
@@ -273,7 +274,7 @@ static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
 
 void wf_engine::run_large(EJob* j, hipStream_t s) {
     const wf_request& r = j->rq;
-    Model* md = new (std::nothrow) Model();
+    std::unique_ptr<Model> md(new (std::nothrow) Model());
     wf_status st = md ? md->init(&r.geom, r.m_dev, s) : fail(WF_E_NOMEM, "host allocation");
     const PointSet *src = nullptr, *rec = nullptr;
     if (st == WF_OK) st = md->check_dt(r.dt);
@@ -304,7 +305,7 @@ void wf_engine::run_large(EJob* j, hipStream_t s) {
         j->gated = false;
         cv_work.notify_all();
     }
-    delete md;   // waits for the model's stream
+    md.reset();   // waits for the model's stream
     j->st = st;
 }
 
@@ -337,7 +338,18 @@ void wf_engine::worker() {
                 j->counted = true;
             }
         }
-        run_large(j, s);
+        try {
+            run_large(j, s);
+        } catch (...) {
+            // a host allocation failed: the request fails, the slot is freed
+            j->st = fail(WF_E_NOMEM, "host allocation failed while serving a request");
+            if (j->gated) {
+                std::lock_guard<std::mutex> lk(mu);
+                --heavy_running;
+                j->gated = false;
+                cv_work.notify_all();
+            }
+        }
         complete(j);
     }
     (void)hipStreamDestroy(s);
