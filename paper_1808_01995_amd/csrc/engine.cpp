@@ -377,6 +377,8 @@ void wf_engine::batcher() {
             }
             if (active.empty() && fresh.empty() && stop) break;
         }
+        size_t fresh_in_active = 0;   // fresh grids already moved to `active`
+        try {
         // set up newly admitted grids (their first step joins this iteration)
         for (EJob* j : fresh) {
             const wf_request& r = j->rq;
@@ -397,6 +399,7 @@ void wf_engine::batcher() {
             }
             j->st = st;
             active.push_back(j);
+            ++fresh_in_active;
         }
         // one iteration: kBatchSteps steps of every active grid
         std::map<std::tuple<int, int, int>, std::vector<EJob*>> groups;
@@ -447,7 +450,8 @@ void wf_engine::batcher() {
         }
         // retire finished grids
         std::vector<EJob*> keep;
-        for (EJob* j : active) {
+        keep.reserve(active.size());   // no allocation once grids start to retire
+        for (EJob*& j : active) {
             if (j->st == WF_OK && j->bf.n < j->bf.nt - 1) {
                 keep.push_back(j);
                 continue;
@@ -458,9 +462,25 @@ void wf_engine::batcher() {
             }
             delete j->md;
             j->md = nullptr;
-            complete(j);
+            EJob* done_job = j;
+            j = nullptr;   // retired: the error path below must not touch it
+            complete(done_job);
         }
         active.swap(keep);
+        } catch (...) {
+            // a host allocation failed: every grid in the batch fails (after
+            // the launches already issued have finished), the slots are freed
+            (void)hipStreamSynchronize(s);
+            for (size_t i = fresh_in_active; i < fresh.size(); ++i) active.push_back(fresh[i]);
+            for (EJob* j : active) {
+                if (!j) continue;   // already retired
+                delete j->md;
+                j->md = nullptr;
+                j->st = fail(WF_E_NOMEM, "host allocation failed while batching");
+                complete(j);
+            }
+            active.clear();
+        }
     }
     if (host_tab) (void)hipHostFree(host_tab);
     dev_tab.reset();
