@@ -195,3 +195,26 @@ def test_one_sample_requests():
         assert r.nt == 1 and torch.all(r.rec_out == 0)
         if r.grad_out is not None:
             assert torch.all(r.grad_out == 0) and r.misfit == 0.0
+
+
+def test_heavy_requests_match_plain_propagator():
+    """Grids above the batching limit (5 M nodes) run on the workers, one at
+    a time while the next is set up: three of them (two forward shots, one
+    gradient) among small requests give the plain propagator's results."""
+    from paper_1808_01995_amd.serve import Server, run_one_shot_baseline, run_stream
+    specs = [{"ndim": 3, "n": 176, "space_order": 8, "steps": 25, "kind": "forward", "seed": 80},
+             {"ndim": 2, "n": 150, "space_order": 4, "steps": 60, "kind": "forward", "seed": 81},
+             {"ndim": 3, "n": 180, "space_order": 4, "steps": 20, "kind": "gradient", "seed": 82, "perturb": 0.05},
+             {"ndim": 3, "n": 190, "space_order": 12, "steps": 15, "kind": "forward", "seed": 83},
+             {"ndim": 2, "n": 120, "space_order": 8, "steps": 40, "kind": "gradient", "seed": 84, "perturb": 0.05}]
+    reqs = _build(specs, nbl=12)
+    assert sum(1 for r in reqs if r.m.numel() > (5 << 20)) == 3
+    srv = Server(hbm_budget_bytes=24 << 30, max_slots=8)
+    st = run_stream(srv, reqs)
+    srv.close()
+    assert st["failed"] == 0
+    base = run_one_shot_baseline(reqs, 24 << 30)
+    for i, (r, (d, g)) in enumerate(zip(reqs, base["outputs"])):
+        assert torch.equal(r.rec_out, d), i
+        if g is not None:
+            assert torch.equal(r.grad_out, g), i
