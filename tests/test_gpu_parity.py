@@ -313,3 +313,28 @@ def test_validation_reports_nonfinite_outputs():
     torch.cuda.synchronize()
     assert not torch.isfinite(d_nan).all()
     prop.close()
+
+
+def test_calls_follow_the_callers_stream():
+    """Work is enqueued on torch's current stream: inputs produced and outputs
+    consumed by torch on a side stream (default priority), with no
+    synchronisation in between, give the default stream's results."""
+    from _harness import noise
+    P = make_problem((34, 29, 31), 6, 8, 50, seed=33, nrec=30)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    y = torch.from_numpy(noise(P.nt, 30, P.dt, 15.0, 4).astype(np.float32)).cuda()
+    d_ref = prop.forward(P.dt, P.nt, P.src_xyz, 2.0 * q, P.rec_xyz) * 3.0
+    g_ref = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, (0.5 * y).contiguous()) + 1.0
+    x_ref = prop.adjoint(P.dt, P.nt, P.rec_xyz, y, P.src_xyz)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        q2 = 2.0 * q                       # produced on the side stream
+        d = prop.forward(P.dt, P.nt, P.src_xyz, q2, P.rec_xyz) * 3.0
+        y2 = (0.5 * y).contiguous()
+        g = prop.gradient(P.dt, P.nt, P.src_xyz, q, P.rec_xyz, y2) + 1.0
+        x = prop.adjoint(P.dt, P.nt, P.rec_xyz, y, P.src_xyz)
+    side.synchronize()
+    assert torch.equal(d, d_ref) and torch.equal(g, g_ref) and torch.equal(x, x_ref)
+    prop.close()
