@@ -52,7 +52,10 @@
  *
  * Streams: `stream` is a hipStream_t passed as void*; NULL means the default
  * stream. Calls enqueue work and return without synchronising, except where
- * noted. A handle is not thread-safe: use one per host thread.
+ * noted. A model used on one stream and then on another orders the new
+ * stream's work after the old one's (an event, no host wait), so calls in
+ * turn on different streams need no synchronisation between them. A handle is
+ * not thread-safe: use one per host thread.
  *
  * Errors: every call returns a wf_status. Argument, shape, CFL, domain and
  * budget errors are detected on the host before anything is enqueued and leave

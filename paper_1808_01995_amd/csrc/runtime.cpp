@@ -460,9 +460,19 @@ wf_status Model::init(const wf_geom* g, const float* m_dev, hipStream_t s) {
     return set_m(m_dev, s);
 }
 
+wf_status Model::use_stream(hipStream_t s) {
+    if (s == last_stream) return WF_OK;
+    if (!order_ev)
+        WF_TRY_RT(hip_check(hipEventCreateWithFlags(&order_ev, hipEventDisableTiming), "event"));
+    WF_TRY_RT(hip_check(hipEventRecord(order_ev, last_stream), "record"));
+    WF_TRY_RT(hip_check(hipStreamWaitEvent(s, order_ev, 0), "wait"));
+    last_stream = s;
+    return WF_OK;
+}
+
 wf_status Model::set_m(const float* m_dev, hipStream_t s) {
     if (!m_dev) return fail(WF_E_ARG, "m is NULL");
-    last_stream = s;
+    WF_TRY_RT(use_stream(s));
     wf_status st;
     if ((st = hip_check(hipMemcpyAsync(d_m.f(), m_dev, (size_t)L.npoints * 4,
                                        hipMemcpyDeviceToDevice, s), "copy m")) != WF_OK)
@@ -528,7 +538,7 @@ wf_status Model::update(const float* grad, double alpha, double lo, double hi, f
     const float flo = (float)lo;
     const float fhi = hi >= (double)FLT_MAX ? FLT_MAX : (float)hi;
     if (!(flo > 0.0f) || !(fhi >= flo)) return fail(WF_E_ARG, "bounds are not representable in FP32");
-    last_stream = s;
+    WF_TRY_RT(use_stream(s));
     // a non-finite gradient value would be clamped silently: refuse it first
     WF_TRY_RT(check_finite(grad, L.npoints, "grad", s));
     WF_TRY_RT(hip_check(launch_update(d_m.f(), grad, (float)alpha, flo, fhi, L.npoints, s), "update"));
@@ -585,7 +595,7 @@ StripGeom Model::strips() const {
 double Model::vmax() const { return 1.0 / std::sqrt(m_min); }
 
 wf_status Model::ensure_kap(double dt, hipStream_t s) {
-    last_stream = s;
+    WF_TRY_RT(use_stream(s));
     if (dt == kap_dt) return WF_OK;
     wf_status st = hip_check(launch_coef(d_m.f(), kap(), L.nx, L.ny, L.nz, L.sx, L.sy, dt, s), "coef");
     if (st != WF_OK) return st;
@@ -662,6 +672,7 @@ Model::~Model() {
     (void)hipStreamSynchronize(last_stream);
     drop_graphs();
     if (ev_in) (void)hipEventDestroy(ev_in);
+    if (order_ev) (void)hipEventDestroy(order_ev);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
     for (auto& c : pcache) delete c.ps;

@@ -135,6 +135,10 @@ struct Model : public wf_model {
     std::vector<PCache> pcache;
     uint64_t tick = 0;
     hipStream_t last_stream = nullptr;   // the stream of the most recent work
+    hipEvent_t order_ev = nullptr;       // orders work on a new stream after the last one
+    // make `s` the model's stream: work enqueued on it from now on starts
+    // after everything enqueued on the previous one (no host wait)
+    wf_status use_stream(hipStream_t s);
     // captured time loops (forward or adjoint), least recently used first out
     struct GraphEntry {
         GraphKey key;

@@ -338,3 +338,26 @@ def test_calls_follow_the_callers_stream():
     side.synchronize()
     assert torch.equal(d, d_ref) and torch.equal(g, g_ref) and torch.equal(x, x_ref)
     prop.close()
+
+
+def test_one_model_on_two_streams_in_turn():
+    """A model used on one stream and then at once on another (no host
+    synchronisation, the inputs ready on both) orders the second call after
+    the first: both records equal those of calls made one after the other
+    on one stream."""
+    P = make_problem((40, 33, 37), 6, 8, 70, seed=35, nrec=30)
+    prop = P.propagator()
+    q1 = torch.from_numpy(P.q32).cuda()
+    q2 = (-0.5 * q1).contiguous()
+    ref1 = prop.forward(P.dt, P.nt, P.src_xyz, q1, P.rec_xyz)
+    ref2 = prop.forward(P.dt, P.nt, P.src_xyz, q2, P.rec_xyz)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        d1 = prop.forward(P.dt, P.nt, P.src_xyz, q1, P.rec_xyz)            # default stream
+        with torch.cuda.stream(side):
+            d2 = prop.forward(P.dt, P.nt, P.src_xyz, q2, P.rec_xyz)        # at once, on the side
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        assert torch.equal(d1, ref1) and torch.equal(d2, ref2)
+    prop.close()
