@@ -21,9 +21,7 @@
 //   request (a grid above kSmallPoints nodes) runs at a time: one such grid
 //   already fills the GPU at its HBM roofline, and two side by side share
 //   the bandwidth while evicting each other from the Infinity Cache (two
-//   concurrent 3D shots took 7 % longer than the same shots in turn). The
-//   next heavy request is set up (model, coefficients, point tables) on a
-//   second worker while one runs, and a third worker serves the others.
+//   concurrent 3D shots took 7 % longer than the same shots in turn).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -139,9 +137,8 @@ namespace {
 // fields no longer sharing the Infinity Cache with nobody)
 constexpr int64_t kSmallPoints = (int64_t)5 << 20;
 constexpr int kBatchSteps = 32;                        // steps per batch iteration
-constexpr int kWorkers = 3;                            // threads for large requests and gradients
-constexpr int kHeavyInWorkers = 2;                     // heavy requests held by workers: one runs, one is set up
-constexpr int kGradShare = 4;                          // a gradient's checkpoints take <= budget / kGradShare
+constexpr int kWorkers = 2;                            // threads for large requests and gradients
+constexpr int kGradShare = 2 * kWorkers;               // a gradient's checkpoints take <= budget / kGradShare
 
 struct EJob {
     uint64_t ticket = 0;
@@ -149,8 +146,7 @@ struct EJob {
     std::vector<double> src, rec;
     bool small = false;
     bool heavy = false;     // grid above kSmallPoints nodes: runs alone among the workers' jobs
-    bool counted = false;   // counted in heavy_in_workers while a worker holds it
-    bool gated = false;     // holds the single run slot of heavy requests
+    bool counted = false;   // counted in heavy_running while it runs
     double due = 0.0;       // arrival (s, steady clock) + estimated run time alone
     int64_t foot = 0;       // bytes reserved at admission
     int64_t grad_cap = 0;   // bytes the gradient's checkpoints may use
@@ -195,8 +191,7 @@ struct wf_engine {
     std::deque<std::pair<uint64_t, wf_status>> done;
     int64_t reserved = 0;
     int running = 0;
-    int heavy_in_workers = 0;   // heavy requests taken by workers (set up or running)
-    int heavy_running = 0;      // heavy requests running on the GPU (0 or 1)
+    int heavy_running = 0;      // heavy requests on the workers (0 or 1)
     int64_t completed = 0;
     bool stop = false;
     uint64_t next_ticket = 1;
@@ -216,8 +211,7 @@ struct wf_engine {
 
     void complete(EJob* j) {
         std::lock_guard<std::mutex> lk(mu);
-        if (j->counted) --heavy_in_workers;
-        if (j->gated) --heavy_running;
+        if (j->counted) --heavy_running;
         reserved -= j->foot;
         --running;
         ++completed;
@@ -252,7 +246,7 @@ static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
         // record scratch (predicted data, residual, partial sums), both
         // increment tables, adjoint pair and gradient, and a checkpoint pool:
         // every forward field if they fit in the gradient's share of the
-        // budget (three workers' gradients together at most three quarters),
+        // budget (the workers' gradients together hold at most half of it),
         // else a revolve pool of that size (the arena is allocated once, so
         // a larger pool costs no allocation, only fewer recomputed steps)
         const int64_t l = r->nt - 1;
@@ -280,13 +274,6 @@ void wf_engine::run_large(EJob* j, hipStream_t s) {
     if (st == WF_OK) st = md->check_dt(r.dt);
     if (st == WF_OK) st = md->points(r.nsrc, j->src.data(), &src);
     if (st == WF_OK) st = md->points(r.nrec, j->rec.data(), &rec);
-    // a heavy request is set up while another runs, then waits for the slot
-    if (st == WF_OK && j->heavy) {
-        std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return heavy_running == 0; });
-        ++heavy_running;
-        j->gated = true;
-    }
     if (st == WF_OK && r.kind == WF_REQ_FORWARD) {
         st = run_forward(*md, r.dt, r.nt, *src, r.src_wav, *rec, r.rec_out, nullptr, 1, s);
         if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
@@ -297,13 +284,6 @@ void wf_engine::run_large(EJob* j, hipStream_t s) {
                           r.d_obs, r.rec_out, &phi);
         if (st == WF_OK && r.misfit_out) *r.misfit_out = phi;
         if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
-    }
-    if (j->gated) {
-        // the GPU work is done (or failed): the next heavy request may run
-        std::lock_guard<std::mutex> lk(mu);
-        --heavy_running;
-        j->gated = false;
-        cv_work.notify_all();
     }
     md.reset();   // waits for the model's stream
     j->st = st;
@@ -319,11 +299,11 @@ void wf_engine::worker() {
         {
             std::unique_lock<std::mutex> lk(mu);
             // earliest expected completion among the requests this worker may
-            // take (a heavy one only while fewer than kHeavyInWorkers are held)
+            // start (no second heavy one while one runs)
             auto pick = [&]() {
                 auto best = large_ready.end();
                 for (auto it = large_ready.begin(); it != large_ready.end(); ++it) {
-                    if ((*it)->heavy && heavy_in_workers >= kHeavyInWorkers) continue;
+                    if ((*it)->heavy && heavy_running > 0) continue;
                     if (best == large_ready.end() || (*it)->due < (*best)->due) best = it;
                 }
                 return best;
@@ -334,21 +314,16 @@ void wf_engine::worker() {
             j = *best;
             large_ready.erase(best);
             if (j->heavy) {
-                ++heavy_in_workers;
+                ++heavy_running;
                 j->counted = true;
             }
         }
         try {
             run_large(j, s);
         } catch (...) {
-            // a host allocation failed: the request fails, the slot is freed
+            // a host allocation failed: the request fails (complete() frees
+            // its slot and its place as the running heavy request)
             j->st = fail(WF_E_NOMEM, "host allocation failed while serving a request");
-            if (j->gated) {
-                std::lock_guard<std::mutex> lk(mu);
-                --heavy_running;
-                j->gated = false;
-                cv_work.notify_all();
-            }
         }
         complete(j);
     }
