@@ -561,11 +561,15 @@ def main():
     _abi.wf_profile_read(_abi.WF_KERNEL_STEP, reset=True)
     _abi.wf_profile_enable(PROFILE_STRIDE)
     torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        evs[i].record()   # on the stream the shot is enqueued on
         shot()
+    evs[-1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    shot_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     _abi.wf_profile_enable(False)
     k_ms, k_n = _abi.wf_profile_read(_abi.WF_KERNEL_STEP, reset=True)
 
@@ -614,6 +618,9 @@ def main():
                                % ("x".join(map(str, prop.comp_shape)), c.steps),
                    "grid": list(prop.comp_shape), "updates": c.steps, "space_order": c.space_order},
         "physical_gpts": round(phys, 3),
+        "shot_device_ms": {"median": round(float(np.median(shot_ms)), 3), "min": round(min(shot_ms), 3),
+                           "max": round(max(shot_ms), 3),
+                           "note": "each timed shot bracketed by events on its stream"},
         "graph_replay": {"ms_per_step": round(el_graph / args.steps * 1e3, 3),
                          "value": round(updates / (el_graph / args.steps) / 1e9, 3),
                          "graph_launches": g_launches,
