@@ -688,9 +688,10 @@ int step_capacity(int ndim, int half, int tile, int mode) {
                                                      ts.bz * ts.by, 0) != hipSuccess ||
         per < 1)
         per = 1;
-    // Beyond 12 resident waves per CU the extra streams only compete for L2
-    // (halo rows get evicted before the neighbouring tile reads them): on the
-    // 336^3 order-8 step, 4 blocks/CU ran 10% slower than 3.
+    // The chunk plan assumes at most 12 resident waves per CU (3 blocks of 4
+    // waves): planning for 16 gave more, shorter chunks, whose extra warm-up
+    // planes cost 10% on the 336^3 order-8 step. (The hardware may still place
+    // a fourth block; capping residency with unused LDS changed nothing.)
     const int waves = ts.bz * ts.by / 64;
     int max_waves = 12;
     if (const char* e = std::getenv("WAVEFD_WAVES_PER_CU")) max_waves = std::max(1, std::atoi(e));
