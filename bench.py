@@ -34,7 +34,6 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_POINT = 16.0     # read u^n, u^{n-1}, kappa; write u^{n+1}
-PROFILE_STRIDE = 16        # HIP events around every 16th step launch in the timed region
 
 
 def log(*a):
@@ -233,7 +232,8 @@ def slab_share(torch, ngpu=8, steps=300, so=8):
 
 def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
     """512^3 physical (592^3 computational), two-layer 1.5/2.5 km/s, one
-    shot per order: GPts/s and the step kernel's algorithmic bandwidth."""
+    shot per order: GPts/s and the step kernel's algorithmic bandwidth (the
+    shot's run of step launches timed by one pair of HIP events)."""
     from paper_1808_01995_amd import Propagator, _abi
     from synthetic import config, ricker
     res = []
@@ -248,11 +248,11 @@ def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
         q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
         rec = torch.empty((c.nt, c.rec.shape[0]), device="cuda")
         prop.forward(dt, 21, c.src, q[:21].contiguous(), c.rec, rec_out=rec[:21])   # warm-up
-        _abi.wf_profile_read(0, reset=True)
-        _abi.wf_profile_enable(True)
+        _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
+        _abi.wf_profile_runs_enable(True)
         el, _ = _timed(torch, lambda: prop.forward(dt, c.nt, c.src, q, c.rec, rec_out=rec))
-        _abi.wf_profile_enable(False)
-        ms, n = _abi.wf_profile_read(0, reset=True)
+        _abi.wf_profile_runs_enable(False)
+        ms, n = _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
         us = ms / max(n, 1) * 1e3
         gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
         if stream is None:
@@ -292,18 +292,24 @@ def gradient_c4(torch, steps=2000, snaps=(-1, 50, 20, -2)):
     # other modes, so no timed call reallocates device memory
     fb = p0.npoints * 4
     slabs = sum(2 * 4 * int(np.prod([c.shape[b] for b in range(3) if b != a])) for a in range(3))
+    l = c.nt - 1
     for s in snaps:
+        _abi.wf_profile_step_launches(0, reset=True)
         el, g = _timed(torch, lambda: p0.gradient(dt, c.nt, c.src, q, c.rec, r, n_checkpoints=s))
+        fwd_counted = _abi.wf_profile_step_launches(0)
+        rev_counted = _abi.wf_profile_step_launches(1)
         if s == -2:
-            fwd_steps = 2 * (c.nt - 1)    # forward sweep + backward rebuild
+            fwd_model = 2 * l - 2     # forward sweep + backward rebuild
             name = "boundary"
             need = 4 * fb + c.nt * slabs * 4
         else:
-            fwd_steps = (c.nt - 1) if s == -1 else 1 + _abi.wf_revolve_forward_steps(c.nt - 1, s)
+            # state 0 needs one step; revolve then advances its optimum
+            fwd_model = l if s == -1 else 1 + _abi.wf_revolve_forward_steps(l, s)
             name = "all" if s == -1 else s
             need = (c.nt + 2 if s == -1 else 2 * s + 5) * fb
         runs.append({"checkpoints": name, "seconds": round(el, 3),
-                     "forward_recompute_steps": fwd_steps, "workspace_GB": round(need / 1e9, 1),
+                     "forward_steps_counted": fwd_counted, "reverse_steps_counted": rev_counted,
+                     "forward_steps_model": fwd_model, "workspace_GB": round(need / 1e9, 1),
                      "gpts_effective": round(p0.npoints * c.steps / el / 1e9, 1)})
         if ref is None:
             ref = g
@@ -316,6 +322,7 @@ def gradient_c4(torch, steps=2000, snaps=(-1, 50, 20, -2)):
         log("c4 gradient s=%s: %s" % (s, runs[-1]))
         del g
     out["gradient"] = runs
+    out["accuracy"] = c4_gradient_accuracy(torch, p0, c, dt, q, steps)
     # torch.autograd path on the physical grid (replicate-pad adjoint folds the layer)
     m_phys = torch.from_numpy((1.0 / v0 ** 2).astype(np.float32)).cuda().requires_grad_(True)
     def ag():
@@ -327,6 +334,39 @@ def gradient_c4(torch, steps=2000, snaps=(-1, 50, 20, -2)):
     out["autograd_forward_plus_backward_s"] = round(el, 3)
     p0.close()
     return out
+
+
+def c4_gradient_accuracy(torch, p0, c, dt, q, steps):
+    """J^T r of the initial model for the seeded band-limited residual stored
+    with the FP64 oracle's result on the plane y = 140 (tests/golden,
+    written by a script that calls only the oracle): rel. L2 over the plane,
+    over its nodes more than 4 cells from every source and receiver node, and
+    the largest element error against the plane's peak."""
+    from synthetic import band_limited_noise
+    path = os.path.join(ROOT, "tests", "golden", "c4_gradient_slice.npz")
+    if steps != 2000 or not os.path.exists(path):
+        return {"note": "stored oracle result not available for %d updates" % steps}
+    gs = np.load(path)
+    y, st = int(gs["y_index"]), int(gs["step"])
+    rn = band_limited_noise(c.nt, c.rec.shape[0], dt, float(gs["noise_f0_hz"]), int(gs["noise_seed"]))
+    gn = p0.gradient(dt, c.nt, c.src, q, c.rec, torch.from_numpy(rn.astype(np.float32)).cuda(),
+                     n_checkpoints=-1)[::st, y, ::st].double().cpu().numpy()
+    ref = gs["gradient"].astype(np.float64)
+    comp = p0.comp_shape
+    near = np.zeros(comp, dtype=bool)
+    for xyz in (c.src, c.rec):
+        s_ = np.floor(np.asarray(xyz) / np.asarray(c.spacing) + c.nbl).astype(int)
+        for i in s_:
+            near[tuple(slice(max(0, a - 4), a + 6) for a in i)] = True
+    away = ~near[::st, y, ::st]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))   # noqa: E731
+    return {"jt_r_plane_rel_l2": rel(gn, ref), "jt_r_plane_away_rel_l2": rel(gn[away], ref[away]),
+            "jt_r_plane_max_element": float(np.abs(gn - ref).max() / np.abs(ref).max()),
+            "bar": "rel. L2 <= 1e-3 vs the FP64 oracle",
+            "note": "a residual both sides share; the workload's own residual (initial minus true "
+                    "model record) is 7e-5 of the records, whose FP32 error (8e-6 of the records) "
+                    "leaves it about 3 % uncertain, so the gradient of the workload's own misfit is "
+                    "only that close to the oracle's (measured 2.8 % on this plane)"}
 
 
 def born_c4(torch, steps=2000):
@@ -496,6 +536,28 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10) -> float:
     return 2.0 * nbytes / el / 1e9
 
 
+def run_rows(torch, args, orders, out):
+    """The further rows named by --rows, added to `out`; returns the set."""
+    rows = set(x for x in args.rows.split(",") if x)
+    if "all" in rows:
+        rows = {"c1", "2d", "c3", "slab", "c4", "born", "fwi", "serve"}
+    if "c1" in rows:
+        out["c1_graph"] = graph_c1(torch)
+    if "2d" in rows:
+        out["large_2d"] = large_2d(torch)
+    if "c3" in rows:
+        out["c3_sweep"] = sweep_c3(torch, orders=orders, steps=args.updates or 500)
+    if "slab" in rows:
+        out["slab_share"] = slab_share(torch)
+    if "c4" in rows:
+        out["c4_gradient"] = gradient_c4(torch)
+    if "born" in rows:
+        out["born"] = born_c4(torch)
+    if "fwi" in rows:
+        out["fwi_multishot"] = fwi_multishot(torch)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -511,7 +573,12 @@ def main():
                     help="requests of the full-size serving stream measured with the headline "
                          "(0: skip; 256 is the whole seeded mix)")
     ap.add_argument("--updates", type=int, default=None,
-                    help="shorter shots (profiling runs only; the benchmark uses 1000)")
+                    help="shorter shots (profiling runs only; the benchmark uses 1000): the headline "
+                         "shot and, with --rows c3, the sweep's shots")
+    ap.add_argument("--orders", default="4,8,12,16", help="space orders of the c3 sweep")
+    ap.add_argument("--rows-only", action="store_true",
+                    help="only the rows of --rows (no headline shot, serving or oracle baseline): "
+                         "short profiling runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -544,6 +611,11 @@ def main():
     if args.profile_kernels:
         profile_kernels(torch)
         return
+    orders = tuple(int(x) for x in args.orders.split(",") if x)
+    if args.rows_only:
+        out = run_rows(torch, args, orders, {})
+        print(json.dumps(out), flush=True)
+        return
 
     c, v, prop, dt, q, rec_out = setup_c2(torch, args.space_order, args.updates)
     npts = prop.npoints
@@ -556,10 +628,13 @@ def main():
         shot()
     torch.cuda.synchronize()
 
-    # every 16th step launch is bracketed by HIP events (the same launch
-    # configuration as the rest; timing every launch would add ~6 % to the shot)
-    _abi.wf_profile_read(_abi.WF_KERNEL_STEP, reset=True)
-    _abi.wf_profile_enable(PROFILE_STRIDE)
+    # each shot's run of step launches is bracketed by one pair of HIP events
+    # on the stream the steps are launched on (two events per shot): the
+    # spans summed over the timed shots, divided by their step launches, give
+    # the average step-launch duration, gaps between the back-to-back
+    # launches included, so that it times every launch of the timed region
+    _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
+    _abi.wf_profile_runs_enable(True)
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
@@ -570,8 +645,8 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     shot_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
-    _abi.wf_profile_enable(False)
-    k_ms, k_n = _abi.wf_profile_read(_abi.WF_KERNEL_STEP, reset=True)
+    _abi.wf_profile_runs_enable(False)
+    k_ms, k_n = _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
 
     # the same shots launched as a captured HIP graph (kernel timing off, so
     # the loop is captured on the first call with an unchanged signature)
@@ -632,6 +707,9 @@ def main():
                      "kernel": "k_step3d<M=4> (fused stencil + damping + time update)",
                      "avg_kernel_ms": round(avg_kernel_ms, 5), "timed_launches": k_n,
                      "launches_in_timed_region": args.steps * c.steps,
+                     "timing_note": "average step launch = the summed spans from before the first to "
+                                    "after the last step launch of each timed shot (two events per shot "
+                                    "on the launch stream) over the launches they cover",
                      "algorithmic_bytes_per_launch": BYTES_PER_POINT * npts,
                      "measured_copy_GBs": round(copy_gbs, 1),
                      "frac_of_measured_copy": round(achieved / copy_gbs, 4),
@@ -651,23 +729,7 @@ def main():
         out["adjoint_gpts"] = round(updates / (time.perf_counter() - t) / 1e9, 3)
 
     prop.close()
-    rows = set(x for x in args.rows.split(",") if x)
-    if "all" in rows:
-        rows = {"c1", "2d", "c3", "slab", "c4", "born", "fwi", "serve"}
-    if "c1" in rows:
-        out["c1_graph"] = graph_c1(torch)
-    if "2d" in rows:
-        out["large_2d"] = large_2d(torch)
-    if "c3" in rows:
-        out["c3_sweep"] = sweep_c3(torch)
-    if "slab" in rows:
-        out["slab_share"] = slab_share(torch)
-    if "c4" in rows:
-        out["c4_gradient"] = gradient_c4(torch)
-    if "born" in rows:
-        out["born"] = born_c4(torch)
-    if "fwi" in rows:
-        out["fwi_multishot"] = fwi_multishot(torch)
+    rows = run_rows(torch, args, orders, out)
     if "serve" in rows and args.serve_requests < 256:
         args.serve_requests = 256
     if args.serve_requests > 0:

@@ -286,11 +286,28 @@ wf_status wf_born(wf_model* model, double dt, int nt,
                   int nsrc, const double* src_xyz, const float* src_wav, const float* dm,
                   int nrec, const double* rec_xyz, float* drec_out, float* rec_out, void* stream);
 
-/* Number of forward time steps the revolve schedule of wf_gradient performs
- * for `steps` updates and `snaps` stored states (steps >= 1, snaps >= 1):
- * the optimal count r l - C(s + r, r - 1) of Griewank and Walther. Pure host
- * function; -1 on bad input. */
+/* Optimal forward-step count of revolve checkpointing (Section "Discrete
+ * adjoint wave-equation and FWI gradient"): for `steps` updates to reverse
+ * with `snaps` stored states (steps >= 1, snaps >= 1), the closed form
+ * r l - C(s + r, r - 1) of Griewank and Walther, r the smallest integer with
+ * C(s + r, s) >= l. Pure host function; -1 on bad input. wf_revolve_schedule
+ * gives the schedule wf_gradient actually runs. */
 int64_t wf_revolve_forward_steps(int64_t steps, int snaps);
+
+#define WF_REVOLVE_ADVANCE  0   /* forward from state `at` to state `arg`       */
+#define WF_REVOLVE_TAKESHOT 1   /* store the current state `at` in slot `arg`   */
+#define WF_REVOLVE_RESTORE  2   /* make slot `arg` (holding state `at`) current */
+#define WF_REVOLVE_REVERSE  3   /* adjoint of step `at` (needs state `at`)      */
+#define WF_REVOLVE_FREE     4   /* release slot `arg`                           */
+
+/* The checkpoint schedule that wf_gradient runs with n_checkpoints = snaps
+ * (same section): the actions in order, state i being the pair
+ * (u^{i+1}, u^i) after i + 1 forward updates, slot 0 holding state 0 from the
+ * start. Writes min(count, cap) actions into kind/at/arg (host arrays, may be
+ * NULL when cap is 0) and returns the total count, or a negative wf_status
+ * for steps < 1 or snaps < 1. Pure host function. */
+int64_t wf_revolve_schedule(int64_t steps, int snaps, int32_t* kind, int64_t* at, int64_t* arg,
+                            int64_t cap);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (tracing aid).                                               */
@@ -299,6 +316,8 @@ int64_t wf_revolve_forward_steps(int64_t steps, int snaps);
 #define WF_KERNEL_STEP    0   /* the fused time-step kernel                   */
 #define WF_KERNEL_INJECT  1   /* sparse injection                              */
 #define WF_KERNEL_SAMPLE  2   /* sparse interpolation                          */
+#define WF_KERNEL_STEP_RUN 3  /* the whole run of step launches of a forward
+                                 or adjoint time loop (wf_profile_runs_enable) */
 
 /* While enabled (process-wide), launches of the three kernels above are
  * bracketed by a pair of HIP events recorded on the stream they run on:
@@ -306,10 +325,28 @@ int64_t wf_revolve_forward_steps(int64_t steps, int snaps);
  * lighter touch on the timed work), none for on == 0. */
 wf_status wf_profile_enable(int on);
 
+/* While on (process-wide, off by default), every wf_forward and wf_adjoint
+ * time loop records one event before its first step launch and one after its
+ * last, on the stream they run on: read as kind WF_KERNEL_STEP_RUN, whose
+ * launch count is the number of step launches those spans cover, so that the
+ * summed time over the count is the average duration of one step launch
+ * (gaps between the back-to-back launches included) with two events per
+ * loop. Like per-launch timing, it suspends graph capture. */
+wf_status wf_profile_runs_enable(int on);
+
 /* Synchronise on the recorded events and return, for kernel `kind`, the summed
  * device time in ms and the number of launches since the last reset; reset != 0
  * clears the record of every kind. */
 wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int reset);
+
+/* Number of step-kernel launches made since the last reset in kernel mode
+ * `mode`: 0 the plain update (forward and adjoint steps, the gradient's
+ * forward and recomputed steps), 1 the update with imaging (the gradient's
+ * reverse steps), 2 the Born background step, 3 the Born scattered step.
+ * Counted on the host for every launch, whether timing is on or not; reset
+ * != 0 clears every mode after reading. Batched launches of the serving
+ * engine are not counted. */
+wf_status wf_profile_step_launches(int mode, int64_t* count, int reset);
 
 /* Bandwidth reference for the roofline (Section "Performance", subsection
  * "Roofline analysis", bounds its kernels by a measured stream bandwidth):
@@ -355,9 +392,31 @@ typedef struct {
 wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** out);
 
 /* Queue a request; returns at once with a ticket. The request's device inputs
- * must stay valid and unchanged until the ticket is reported done. Requests
- * that could never fit the budget fail here with WF_E_BUDGET. */
+ * must be complete when the call is made (no work still writing them) and
+ * stay valid and unchanged until the ticket is reported done. Requests that
+ * could never fit the budget fail here with WF_E_BUDGET. The same as
+ * wf_engine_submit_on(engine, req, NULL, 0, ticket). */
 wf_status wf_engine_submit(wf_engine* engine, const wf_request* req, uint64_t* ticket);
+
+/* Queue a request whose device inputs are produced by work on the caller's
+ * `stream` (hipStream_t as void*, NULL the default stream): with ordered != 0
+ * the call records an event on `stream` and every piece of the engine's work
+ * on the request waits for it on the device, so the caller needs no
+ * synchronisation between producing the inputs and submitting (work queued
+ * on `stream` after the call is not waited for). Returns at once, as
+ * wf_engine_submit, which it equals for ordered == 0. The inputs must stay
+ * valid and unchanged until the ticket is reported done; outputs are complete
+ * when it is. */
+wf_status wf_engine_submit_on(wf_engine* engine, const wf_request* req, void* stream, int ordered,
+                              uint64_t* ticket);
+
+/* Device bytes the engine reserves from a budget of `hbm_budget_bytes` for
+ * `req` when it admits it (its fields, coefficients, sparse and injection
+ * tables, records and, for a gradient, the checkpoint memory it is given):
+ * an upper bound on what serving the request allocates from the budget. A
+ * request whose reservation exceeds the engine's budget is refused at
+ * submission. Pure host function (reads the host coordinates). */
+wf_status wf_engine_request_bytes(const wf_request* req, int64_t hbm_budget_bytes, int64_t* bytes);
 
 /* Advance the engine: admit queued requests as slots and memory free up, issue
  * their next batch of steps, and report finished tickets (up to `cap`) with

@@ -109,14 +109,19 @@ def _load():
         "wf_born": (I, [P, D, I, I, P, P, P, I, P, P, P, P]),
         "wf_model_update": (I, [P, P, D, D, D, P, P]),
         "wf_revolve_forward_steps": (I64, [I64, I]),
+        "wf_revolve_schedule": (I64, [I64, I, P, P, P, I64]),
         "wf_profile_enable": (I, [I]),
+        "wf_profile_runs_enable": (I, [I]),
         "wf_profile_read": (I, [I, P, P, I]),
+        "wf_profile_step_launches": (I, [I, P, I]),
         "wf_stream_bandwidth": (I, [I64, I, P]),
         "wf_model_ghost_nonzero": (I, [P, P]),
         "wf_validate_enable": (I, [I]),
         "wf_engine_create": (I, [I64, I, P]),
         "wf_engine_submit": (I, [P, ctypes.POINTER(wf_request), P]),
+        "wf_engine_submit_on": (I, [P, ctypes.POINTER(wf_request), P, I, P]),
         "wf_engine_poll": (I, [P, P, P, I, P, I]),
+        "wf_engine_request_bytes": (I, [ctypes.POINTER(wf_request), I64, P]),
         "wf_engine_stats": (I, [P, P, P, P, P]),
         "wf_engine_destroy": (I, [P]),
     }
@@ -134,9 +139,10 @@ EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf
            "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches", "wf_graph_enable",
            "wf_model_trim",
            "wf_model_destroy", "wf_forward", "wf_adjoint",
-           "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_profile_enable", "wf_profile_read",
+           "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_revolve_schedule",
+           "wf_profile_enable", "wf_profile_runs_enable", "wf_profile_read", "wf_profile_step_launches",
            "wf_stream_bandwidth", "wf_model_ghost_nonzero", "wf_validate_enable",
-           "wf_engine_create", "wf_engine_submit",
+           "wf_engine_create", "wf_engine_submit", "wf_engine_submit_on", "wf_engine_request_bytes",
            "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
 
 
@@ -312,14 +318,46 @@ def wf_revolve_forward_steps(steps: int, snaps: int) -> int:
     return int(lib.wf_revolve_forward_steps(int(steps), int(snaps)))
 
 
+WF_REVOLVE_ADVANCE, WF_REVOLVE_TAKESHOT, WF_REVOLVE_RESTORE, WF_REVOLVE_REVERSE, WF_REVOLVE_FREE = range(5)
+
+
+def wf_revolve_schedule(steps: int, snaps: int):
+    """The checkpoint schedule wf_gradient runs: a list of (kind, at, arg)."""
+    n = int(lib.wf_revolve_schedule(int(steps), int(snaps), None, None, None, 0))
+    if n < 0:
+        raise WaveFDError(n, wf_last_error())
+    kind = np.zeros(n, dtype=np.int32)
+    at = np.zeros(n, dtype=np.int64)
+    arg = np.zeros(n, dtype=np.int64)
+    m = int(lib.wf_revolve_schedule(int(steps), int(snaps), kind.ctypes.data, at.ctypes.data,
+                                    arg.ctypes.data, n))
+    if m != n:
+        raise WaveFDError(WF_E_STATE, "schedule length changed")
+    return list(zip(kind.tolist(), at.tolist(), arg.tolist()))
+
+
 WF_KERNEL_STEP = 0
 WF_KERNEL_INJECT = 1
 WF_KERNEL_SAMPLE = 2
+WF_KERNEL_STEP_RUN = 3
 
 
 def wf_profile_enable(on):
     """True/1: time every launch; n > 1: every n-th launch of each kernel; 0: off."""
     _check(lib.wf_profile_enable(int(on)))
+
+
+def wf_profile_runs_enable(on):
+    """Time each forward/adjoint loop's run of step launches as one span."""
+    _check(lib.wf_profile_runs_enable(1 if on else 0))
+
+
+def wf_profile_step_launches(mode: int, reset: bool = False) -> int:
+    """Step-kernel launches in `mode` (0 plain, 1 imaging, 2 Born source,
+    3 volume source) since the last reset."""
+    n = ctypes.c_int64()
+    _check(lib.wf_profile_step_launches(int(mode), ctypes.byref(n), 1 if reset else 0))
+    return n.value
 
 
 def wf_profile_read(kind: int, reset: bool = False):
@@ -362,6 +400,21 @@ def wf_engine_submit(engine, req: wf_request) -> int:
     t = ctypes.c_uint64()
     _check(lib.wf_engine_submit(engine, ctypes.byref(req), ctypes.byref(t)))
     return int(t.value)
+
+
+def wf_engine_submit_on(engine, req: wf_request, stream=None) -> int:
+    """Submit with the engine's work ordered after what the caller queued on
+    `stream` (torch's current stream by default): no host synchronisation."""
+    t = ctypes.c_uint64()
+    _check(lib.wf_engine_submit_on(engine, ctypes.byref(req), _stream(stream), 1, ctypes.byref(t)))
+    return int(t.value)
+
+
+def wf_engine_request_bytes(req: wf_request, hbm_budget_bytes: int) -> int:
+    """Bytes the engine reserves for `req` under that budget."""
+    b = ctypes.c_int64()
+    _check(lib.wf_engine_request_bytes(ctypes.byref(req), int(hbm_budget_bytes), ctypes.byref(b)))
+    return b.value
 
 
 def wf_engine_poll(engine, cap: int = 64, wait_ms: int = 0):

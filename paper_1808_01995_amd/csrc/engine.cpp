@@ -23,10 +23,12 @@
 //   the bandwidth while evicting each other from the Infinity Cache (two
 //   concurrent 3D shots took 7 % longer than the same shots in turn).
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -139,6 +141,7 @@ constexpr int64_t kSmallPoints = (int64_t)5 << 20;
 constexpr int kBatchSteps = 32;                        // steps per batch iteration
 constexpr int kWorkers = 2;                            // threads for large requests and gradients
 constexpr int kGradShare = 2 * kWorkers;               // a gradient's checkpoints take <= budget / kGradShare
+constexpr int kThrottleSteps = 16;                     // step launches a worker keeps queued (x2)
 
 struct EJob {
     uint64_t ticket = 0;
@@ -155,6 +158,14 @@ struct EJob {
     BatchFwd bf;
     const PointSet* ps_src = nullptr;
     const PointSet* ps_rec = nullptr;
+    hipEvent_t ready = nullptr;   // recorded on the submitter's stream: the inputs are complete
+    ~EJob() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
+    // make work on `s` wait until the submitter's inputs are complete
+    wf_status wait_inputs(hipStream_t s) const {
+        return ready ? hip_check(hipStreamWaitEvent(s, ready, 0), "wait for the request's inputs") : WF_OK;
+    }
 };
 
 double now_s() {
@@ -173,6 +184,36 @@ int64_t field_bytes_of(const wf_geom* g) {
     Layout L;
     L.init(g);
     return L.field_bytes();
+}
+
+// Increment slots of the fused injection of a point set, bounded from above
+// without building its tables: an entry is one (x, y, z / 4) group of nodes
+// (the 4 z nodes of the owning thread; z tiles start at multiples of 4), with
+// 4 slots, and every corner node of every point's cell may be one.
+int64_t fused_slots_bound(const wf_geom* g, const Layout& L, int npts, const double* xyz) {
+    const int D = g->ndim;
+    const int64_t n[3] = {L.nx, D == 3 ? L.ny : 1, L.nz};
+    std::vector<int64_t> keys;
+    keys.reserve((size_t)npts << D);
+    for (int p = 0; p < npts; ++p) {
+        int64_t base[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+            const int la = D == 3 ? a : (a == 0 ? 0 : 2);   // layout axis of coordinate a
+            const double s = (xyz[(size_t)p * D + a] - g->origin[a]) / g->h[a] + g->nbl;
+            int64_t i = std::isfinite(s) ? (int64_t)std::floor(s) : 0;
+            base[la] = std::max<int64_t>(0, std::min<int64_t>(i, n[la] - 2));
+        }
+        for (int c = 0; c < (1 << D); ++c) {
+            int64_t v[3] = {base[0], base[1], base[2]};
+            v[0] += c & 1;
+            if (D == 3) v[1] += (c >> 1) & 1;
+            v[2] += (c >> (D - 1)) & 1;
+            keys.push_back((v[0] * n[1] + v[1]) * ((n[2] + 3) / 4) + v[2] / 4);
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+    const int64_t entries = std::unique(keys.begin(), keys.end()) - keys.begin();
+    return 4 * entries;
 }
 
 }  // namespace
@@ -226,8 +267,10 @@ struct wf_engine {
     void batcher();
 };
 
-// footprint estimate of a request (bytes of the arena it may occupy)
-static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
+// footprint estimate of a request (bytes of the arena it may occupy); the
+// coordinates are the host copies held by the job
+static wf_status footprint(const wf_request* r, const double* src_xyz, const double* rec_xyz,
+                           int64_t budget, EJob* j) {
     Layout L;
     L.init(&r->geom);
     const int64_t fb = L.field_bytes();
@@ -235,8 +278,9 @@ static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
     const int K = 1 << r->geom.ndim;
     const int64_t pts = (int64_t)(r->nsrc + r->nrec) * K;
     const int64_t tables = pts * 64 + (int64_t)L.nx * 4 * 1024 + ((int64_t)16 << 20);
-    const int64_t inc_src = (int64_t)r->nt * r->nsrc * K * 4;
-    const int64_t inc_rec = (int64_t)r->nt * r->nrec * K * 4;
+    // precomputed increments of the fused injection: one float per slot and row
+    const int64_t inc_src = (int64_t)r->nt * fused_slots_bound(&r->geom, L, r->nsrc, src_xyz) * 4;
+    const int64_t inc_rec = (int64_t)r->nt * fused_slots_bound(&r->geom, L, r->nrec, rec_xyz) * 4;
     const int64_t model = dense + 3 * fb + ((int64_t)1 << 20);
     if (r->kind == WF_REQ_FORWARD) {
         j->foot = model + inc_src + tables;
@@ -269,7 +313,8 @@ static wf_status footprint(const wf_request* r, int64_t budget, EJob* j) {
 void wf_engine::run_large(EJob* j, hipStream_t s) {
     const wf_request& r = j->rq;
     std::unique_ptr<Model> md(new (std::nothrow) Model());
-    wf_status st = md ? md->init(&r.geom, r.m_dev, s) : fail(WF_E_NOMEM, "host allocation");
+    wf_status st = md ? j->wait_inputs(s) : fail(WF_E_NOMEM, "host allocation");
+    if (st == WF_OK) st = md->init(&r.geom, r.m_dev, s);
     const PointSet *src = nullptr, *rec = nullptr;
     if (st == WF_OK) st = md->check_dt(r.dt);
     if (st == WF_OK) st = md->points(r.nsrc, j->src.data(), &src);
@@ -291,9 +336,14 @@ void wf_engine::run_large(EJob* j, hipStream_t s) {
 
 void wf_engine::worker() {
     (void)hipSetDevice(device);
-    set_thread_arena(arena);
     hipStream_t s = nullptr;
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    set_thread_arena(arena, s);
+    // a heavy request keeps only a few milliseconds of launches queued, so
+    // that requests arriving meanwhile (the batcher's launches, the other
+    // worker's) are not queued behind its whole time loop when their streams
+    // share a hardware queue
+    set_thread_throttle(kThrottleSteps);
     for (;;) {
         EJob* j = nullptr;
         {
@@ -333,9 +383,9 @@ void wf_engine::worker() {
 
 void wf_engine::batcher() {
     (void)hipSetDevice(device);
-    set_thread_arena(arena);
     hipStream_t s = nullptr;
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    set_thread_arena(arena, s);
     BatchJob* host_tab = nullptr;
     int cap_tab = 0;
     DevBuf dev_tab;
@@ -358,7 +408,8 @@ void wf_engine::batcher() {
         for (EJob* j : fresh) {
             const wf_request& r = j->rq;
             j->md = new (std::nothrow) Model();
-            wf_status st = j->md ? j->md->init(&r.geom, r.m_dev, s) : fail(WF_E_NOMEM, "host allocation");
+            wf_status st = j->md ? j->wait_inputs(s) : fail(WF_E_NOMEM, "host allocation");
+            if (st == WF_OK) st = j->md->init(&r.geom, r.m_dev, s);
             if (st == WF_OK) st = j->md->check_dt(r.dt);
             if (st == WF_OK) st = j->md->points(r.nsrc, j->src.data(), &j->ps_src);
             if (st == WF_OK) st = j->md->points(r.nrec, j->rec.data(), &j->ps_rec);
@@ -399,6 +450,7 @@ void wf_engine::batcher() {
             std::vector<G> gl;
             int off = 0;
             for (auto& g : groups) {
+                if (st != WF_OK) break;   // no table to fill
                 int begin = 0;
                 for (size_t q = 0; q < g.second.size(); ++q) {
                     host_tab[off + (int)q] = batch_forward_job(g.second[q]->bf, kBatchSteps, begin);
@@ -493,6 +545,11 @@ wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** 
 }
 
 wf_status wf_engine_submit(wf_engine* e, const wf_request* r, uint64_t* ticket) {
+    return wf_engine_submit_on(e, r, nullptr, 0, ticket);
+}
+
+wf_status wf_engine_submit_on(wf_engine* e, const wf_request* r, void* stream, int ordered,
+                              uint64_t* ticket) {
     try {
         if (!e || !r || !ticket) return fail(WF_E_ARG, "NULL argument");
         wf_status st = check_geom(&r->geom);
@@ -513,7 +570,14 @@ wf_status wf_engine_submit(wf_engine* e, const wf_request* r, uint64_t* ticket) 
         if (r->nrec > 0) j->rec.assign(r->rec_xyz, r->rec_xyz + (size_t)r->nrec * D);
         j->rq.src_xyz = nullptr;
         j->rq.rec_xyz = nullptr;
-        st = footprint(r, e->budget, j);
+        st = footprint(r, j->src.data(), j->rec.data(), e->budget, j);
+        if (st == WF_OK && ordered) {
+            // the engine's work on this request waits for what the caller has
+            // queued on `stream` so far (its inputs), with no host wait
+            st = hip_check(hipEventCreateWithFlags(&j->ready, hipEventDisableTiming), "event");
+            if (st == WF_OK)
+                st = hip_check(hipEventRecord(j->ready, reinterpret_cast<hipStream_t>(stream)), "event record");
+        }
         if (st != WF_OK) {
             delete j;
             return st;
@@ -526,6 +590,25 @@ wf_status wf_engine_submit(wf_engine* e, const wf_request* r, uint64_t* ticket) 
         return WF_OK;
     } catch (...) {
         return fail(WF_E_NOMEM, "submit failed");
+    }
+}
+
+wf_status wf_engine_request_bytes(const wf_request* r, int64_t budget, int64_t* bytes) {
+    try {
+        if (!r || !bytes) return fail(WF_E_ARG, "NULL argument");
+        wf_status st = check_geom(&r->geom);
+        if (st != WF_OK) return st;
+        if (r->nt < 1 || r->nsrc < 0 || r->nrec < 0) return fail(WF_E_ARG, "bad nt or point counts");
+        if ((r->nsrc > 0 && !r->src_xyz) || (r->nrec > 0 && !r->rec_xyz))
+            return fail(WF_E_ARG, "missing coordinates");
+        if (budget <= 0) return fail(WF_E_ARG, "budget must be > 0");
+        EJob j;
+        (void)footprint(r, r->src_xyz, r->rec_xyz, budget, &j);   // WF_E_BUDGET still sets j.foot
+        clear_error();
+        *bytes = j.foot;
+        return WF_OK;
+    } catch (...) {
+        return fail(WF_E_NOMEM, "host allocation failed");
     }
 }
 

@@ -1,4 +1,6 @@
-// Per-kernel device timing with HIP events (enabled on demand).
+// Per-kernel device timing with HIP events (enabled on demand), whole runs
+// of step launches timed as one span, and per-mode counts of step launches.
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -8,18 +10,23 @@ namespace wf {
 
 namespace {
 
+constexpr int kKinds = 4;         // WF_KERNEL_STEP .. WF_KERNEL_STEP_RUN
+
 struct Rec {
     int kind;
     hipEvent_t a, b;
+    int64_t count;                // launches the record covers
 };
 
 std::mutex g_mu;
 int g_on = 0;                     // sampling stride, 0 = off
+bool g_runs = false;              // whole runs of step launches timed as one span
 int64_t g_seen[3] = {0, 0, 0};    // launches seen per kind while enabled
 std::vector<Rec> g_recs;          // recorded, not yet read
 std::vector<hipEvent_t> g_free;   // reusable events
-double g_ms[3] = {0, 0, 0};
-int64_t g_n[3] = {0, 0, 0};
+double g_ms[kKinds] = {0, 0, 0, 0};
+int64_t g_n[kKinds] = {0, 0, 0, 0};
+std::atomic<int64_t> g_launches[kModeCount];   // step launches per mode (always counted)
 
 hipEvent_t get_event() {
     if (!g_free.empty()) {
@@ -46,9 +53,9 @@ wf_status drain(bool wait) {
             continue;
         }
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.kind >= 0 && r.kind < 3) {
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.kind >= 0 && r.kind < kKinds) {
             g_ms[r.kind] += ms;
-            g_n[r.kind] += 1;
+            g_n[r.kind] += r.count;
         }
         g_free.push_back(r.a);
         g_free.push_back(r.b);
@@ -62,7 +69,43 @@ wf_status drain(bool wait) {
 
 bool profiling_active() {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_on > 0;
+    return g_on > 0 || g_runs;
+}
+
+void count_step_launch(int mode) {
+    if (mode >= 0 && mode < kModeCount) g_launches[mode].fetch_add(1, std::memory_order_relaxed);
+}
+
+RunSpan::RunSpan(hipStream_t st) : s(st) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_runs) return;
+    if (g_recs.size() > 4096) drain(false);
+    a = get_event();
+    b = get_event();
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+        if (a) g_free.push_back(a);
+        if (b) g_free.push_back(b);
+        a = b = nullptr;
+    }
+}
+
+void RunSpan::finish(int64_t launches) {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (launches > 0 && hipEventRecord(b, s) == hipSuccess) {
+        g_recs.push_back({WF_KERNEL_STEP_RUN, a, b, launches});
+    } else {
+        g_free.push_back(a);
+        g_free.push_back(b);
+    }
+    a = b = nullptr;
+}
+
+RunSpan::~RunSpan() {
+    if (!a) return;   // finished, or not timing
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_free.push_back(a);
+    g_free.push_back(b);
 }
 
 ProfScope::ProfScope(int k, hipStream_t st) : kind(k), s(st) {
@@ -83,7 +126,7 @@ ProfScope::~ProfScope() {
     if (!a) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (hipEventRecord(b, s) == hipSuccess) {
-        g_recs.push_back({kind, a, b});
+        g_recs.push_back({kind, a, b, 1});
     } else {
         g_free.push_back(a);
         g_free.push_back(b);
@@ -104,15 +147,29 @@ wf_status wf_profile_enable(int on) {
     return WF_OK;
 }
 
+wf_status wf_profile_runs_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_runs = on != 0;
+    return WF_OK;
+}
+
+wf_status wf_profile_step_launches(int mode, int64_t* count, int reset) {
+    if (mode < 0 || mode >= kModeCount) return fail(WF_E_ARG, "unknown step mode %d", mode);
+    if (count) *count = g_launches[mode].load();
+    if (reset)
+        for (int k = 0; k < kModeCount; ++k) g_launches[k].store(0);
+    return WF_OK;
+}
+
 wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int reset) {
-    if (kind < 0 || kind > 2) return fail(WF_E_ARG, "unknown kernel kind %d", kind);
+    if (kind < 0 || kind >= kKinds) return fail(WF_E_ARG, "unknown kernel kind %d", kind);
     std::lock_guard<std::mutex> lk(g_mu);
     wf_status st = drain(true);
     if (st != WF_OK) return st;
     if (total_ms) *total_ms = g_ms[kind];
     if (launches) *launches = g_n[kind];
     if (reset)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kKinds; ++k) {
             g_ms[k] = 0.0;
             g_n[k] = 0;
         }

@@ -31,6 +31,33 @@ namespace {
         if (st__ != WF_OK) return st__;      \
     } while (0)
 
+// Queue-depth limit of the calling thread's time loops (0: none).
+thread_local int t_throttle = 0;
+struct ThrottleState {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool armed[2] = {false, false};
+    int64_t count = 0;
+    ~ThrottleState() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+thread_local ThrottleState t_thr;
+
+// After every step launch: every t_throttle launches, wait on the host for
+// the event recorded t_throttle launches before, then record a new one.
+wf_status throttle_tick(hipStream_t s) {
+    if (t_throttle <= 0) return WF_OK;
+    if (++t_thr.count % t_throttle != 0) return WF_OK;
+    const int k = (int)((t_thr.count / t_throttle) & 1);
+    if (!t_thr.ev[k])
+        WF_TRY(hip_check(hipEventCreateWithFlags(&t_thr.ev[k], hipEventDisableTiming), "event"));
+    if (t_thr.armed[k]) WF_TRY(hip_check(hipEventSynchronize(t_thr.ev[k]), "throttle wait"));
+    WF_TRY(hip_check(hipEventRecord(t_thr.ev[k], s), "event"));
+    t_thr.armed[k] = true;
+    return WF_OK;
+}
+
 wf_status step(StepParams& p, const Model& md, const float* cur, const float* old, float* out,
                int mode, float* grad, const float* ufwd, hipStream_t s) {
     p.cur = cur;
@@ -38,8 +65,12 @@ wf_status step(StepParams& p, const Model& md, const float* cur, const float* ol
     p.out = out;
     p.grad = grad;
     p.ufwd = ufwd;
-    ProfScope prof(WF_KERNEL_STEP, s);
-    return hip_check(launch_step(p, md.geom.ndim, md.half, mode, s), "stencil launch");
+    count_step_launch(mode);
+    {
+        ProfScope prof(WF_KERNEL_STEP, s);
+        WF_TRY(hip_check(launch_step(p, md.geom.ndim, md.half, mode, s), "stencil launch"));
+    }
+    return throttle_tick(s);
 }
 
 wf_status inject(const Model& md, const PointSet& ps, const float* vals, float* field, float* grad,
@@ -202,7 +233,7 @@ wf_status launch_graph(Model& md, Model::GraphEntry& e, hipStream_t s) {
 // signature ran eagerly in one of the last calls; else run it eagerly.
 template <class F>
 wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enqueue) {
-    if (!graphs_enabled() || profiling_active()) return enqueue(s);
+    if (!graphs_enabled() || profiling_active() || t_throttle > 0) return enqueue(s);
     for (Model::GraphEntry& e : md.graphs)
         if (e.key == key) return launch_graph(md, e, s);
     auto it = std::find(md.seen.begin(), md.seen.end(), key);
@@ -252,6 +283,12 @@ wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enq
 
 void set_graphs_enabled(bool on) { graph_switch().store(on ? 1 : 0); }
 
+void set_thread_throttle(int steps) {
+    t_throttle = std::max(0, steps);
+    t_thr.count = 0;
+    t_thr.armed[0] = t_thr.armed[1] = false;
+}
+
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
                       hipStream_t s) {
@@ -275,6 +312,7 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
         WF_TRY(inj.enqueue(q));
         if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, q), "fill"));
         StepParams ps = p;
+        RunSpan span(q);
         for (int n = 0; n + 1 < nt; ++n) {
             // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
             inj.configure(ps, n);
@@ -286,6 +324,7 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
                                                 L.nx, L.ny, L.nz, L.sx, L.sy, q), "save"));
             std::swap(A, B);
         }
+        span.finish(nt - 1);
         if (nt > 1) WF_TRY(sample(rec, A, rec_out + (int64_t)(nt - 1) * rec.npts, q));
         return WF_OK;
     };
@@ -313,6 +352,7 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
         WF_TRY(inj.enqueue(q));
         if (nt == 1 && src.npts > 0) WF_TRY(hip_check(launch_fill(src_out, src.npts, 0.0f, q), "fill"));
         StepParams ps = p;
+        RunSpan span(q);
         for (int n = nt - 2; n >= 0; --n) {
             // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
             inj.configure(ps, n + 1);
@@ -321,6 +361,7 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
             WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, ps, q));
             std::swap(A, B);
         }
+        span.finish(nt - 1);
         if (nt > 1) WF_TRY(sample(src, A, src_out, q));
         return WF_OK;
     };

@@ -109,3 +109,22 @@ wf_status revolve_schedule(int64_t steps, int snaps, std::vector<RevolveAction>&
 }
 
 }  // namespace wf
+
+extern "C" int64_t wf_revolve_schedule(int64_t steps, int snaps, int32_t* kind, int64_t* at,
+                                       int64_t* arg, int64_t cap) {
+    try {
+        std::vector<wf::RevolveAction> acts;
+        const wf_status st = wf::revolve_schedule(steps, snaps, acts);
+        if (st != WF_OK) return st;
+        const int64_t n = (int64_t)acts.size();
+        if (cap > 0 && (!kind || !at || !arg)) return wf::fail(WF_E_ARG, "NULL output array");
+        for (int64_t i = 0; i < std::min(n, cap); ++i) {
+            kind[i] = (int32_t)acts[(size_t)i].kind;
+            at[i] = acts[(size_t)i].at;
+            arg[i] = acts[(size_t)i].arg;
+        }
+        return n;
+    } catch (...) {
+        return wf::fail(WF_E_NOMEM, "host allocation failed");
+    }
+}

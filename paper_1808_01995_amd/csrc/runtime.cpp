@@ -124,7 +124,11 @@ std::vector<float> eta_profile(const wf_geom* g, int axis) {
 // device memory helpers
 // ---------------------------------------------------------------------------
 static thread_local Arena* t_arena = nullptr;
-void set_thread_arena(Arena* a) { t_arena = a; }
+static thread_local hipStream_t t_arena_stream = nullptr;
+void set_thread_arena(Arena* a, hipStream_t s) {
+    t_arena = a;
+    t_arena_stream = a ? s : nullptr;
+}
 
 int64_t device_free_bytes() {
     if (t_arena) return arena_largest_free(t_arena);
@@ -139,12 +143,20 @@ int64_t device_free_bytes() {
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset() {
     if (ptr) {
-        if (arena) arena_free(arena, ptr);
-        else hipFree(ptr);
+        if (arena) {
+            // hipFree waits for the device; the arena does not, so wait for
+            // the stream the buffer's work was queued on (a no-op when that
+            // work is done, as on every successful path)
+            if (owner) (void)hipStreamSynchronize(owner);
+            arena_free(arena, ptr);
+        } else {
+            hipFree(ptr);
+        }
     }
     ptr = nullptr;
     bytes = 0;
     arena = nullptr;
+    owner = nullptr;
 }
 wf_status DevBuf::alloc(int64_t nbytes) {
     reset();
@@ -155,6 +167,7 @@ wf_status DevBuf::alloc(int64_t nbytes) {
         ptr = q;
         bytes = nbytes;
         arena = t_arena;
+        owner = t_arena_stream;
         return WF_OK;
     }
     void* p = nullptr;

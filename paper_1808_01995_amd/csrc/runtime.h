@@ -34,14 +34,17 @@ void arena_free(Arena* a, void* p);
 int64_t arena_used(const Arena* a);
 int64_t arena_largest_free(Arena* a);
 // While set on a thread, DevBuf allocations made by that thread come from the
-// arena (and are returned to it when freed, from any thread).
-void set_thread_arena(Arena* a);
+// arena (and are returned to it when freed, from any thread). `s` is the
+// stream that thread enqueues its work on: freeing such a buffer first waits
+// for it, so that no queued kernel still uses memory the arena hands out again.
+void set_thread_arena(Arena* a, hipStream_t s = nullptr);
 
 // Owned device allocation.
 struct DevBuf {
     void* ptr = nullptr;
     int64_t bytes = 0;
     Arena* arena = nullptr;
+    hipStream_t owner = nullptr;   // arena buffers: the stream to wait for before freeing
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -195,10 +198,27 @@ struct ProfScope {
     ProfScope(int kind, hipStream_t s);
     ~ProfScope();
 };
+// While run timing is on: one event before a time loop's first step launch
+// and one after its last (finish(n) with the loop's n step launches).
+struct RunSpan {
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit RunSpan(hipStream_t s);
+    void finish(int64_t launches);
+    ~RunSpan();
+};
+// Every step launch is counted per kernel mode (wf_profile_step_launches).
+void count_step_launch(int mode);
 
 // Time loops (propagate.cpp).
 // Process-wide switch for capturing time loops as HIP graphs.
 void set_graphs_enabled(bool on);
+// While positive on a thread, the time loops that thread enqueues keep at
+// most about 2 x `steps` step launches queued ahead of the device (a host
+// wait on an event every `steps` launches), so that work other streams
+// submit meanwhile is not stuck behind a whole loop in a shared hardware
+// queue. Loops are not captured as graphs then.
+void set_thread_throttle(int steps);
 // post-run checks that every output value is finite (process-wide switch,
 // initially on when WAVEFD_VALIDATE=1)
 bool validation_enabled();

@@ -117,6 +117,29 @@ def gradient_memory(budget: int, npoints: int, nt: int, nrec: int):
     return 0, max(5 * fb, share) + 3 * fb + 2 * nt * nrec * 4 + (1 << 20)
 
 
+def request_struct(r: Request) -> "_abi.wf_request":
+    """The C request for `r` (its host coordinate arrays are kept on r)."""
+    q = _abi.wf_request()
+    q.kind = r.kind
+    q.geom = r.geom
+    q.m_dev = r.m.data_ptr()
+    q.dt = r.dt
+    q.nt = r.nt
+    r._src = np.ascontiguousarray(r.src_xyz, dtype=np.float64)
+    r._rec = np.ascontiguousarray(r.rec_xyz, dtype=np.float64)
+    q.nsrc = r._src.shape[0]
+    q.src_xyz = r._src.ctypes.data
+    q.src_wav = r.src_wav.data_ptr()
+    q.nrec = r._rec.shape[0]
+    q.rec_xyz = r._rec.ctypes.data
+    q.rec_out = r.rec_out.data_ptr()
+    if r.kind == _abi.WF_REQ_GRADIENT:
+        q.d_obs = r.d_obs.data_ptr()
+        q.grad_out = r.grad_out.data_ptr()
+        q.misfit_out = ctypes.addressof(r._misfit_buf)
+    return q
+
+
 class Server:
     """Client of one native engine (HBM budget, slot limit)."""
 
@@ -131,28 +154,13 @@ class Server:
         self.completed: List[Request] = []
 
     def submit(self, r: Request) -> int:
-        torch.cuda.synchronize()   # the request's inputs are complete before the engine reads them
-        q = _abi.wf_request()
-        q.kind = r.kind
-        q.geom = r.geom
-        q.m_dev = r.m.data_ptr()
-        q.dt = r.dt
-        q.nt = r.nt
-        r._src = np.ascontiguousarray(r.src_xyz, dtype=np.float64)
-        r._rec = np.ascontiguousarray(r.rec_xyz, dtype=np.float64)
-        q.nsrc = r._src.shape[0]
-        q.src_xyz = r._src.ctypes.data
-        q.src_wav = r.src_wav.data_ptr()
-        q.nrec = r._rec.shape[0]
-        q.rec_xyz = r._rec.ctypes.data
-        q.rec_out = r.rec_out.data_ptr()
-        if r.kind == _abi.WF_REQ_GRADIENT:
-            q.d_obs = r.d_obs.data_ptr()
-            q.grad_out = r.grad_out.data_ptr()
-            q.misfit_out = ctypes.addressof(r._misfit_buf)
+        """Queue `r`; the engine's work on it is ordered after the work the
+        caller has queued on torch's current stream (which produced its
+        inputs): no synchronisation of the device or the stream."""
+        q = request_struct(r)
         if not r.arrival:
             r.arrival = time.perf_counter()
-        t = _abi.wf_engine_submit(self.handle, q)
+        t = _abi.wf_engine_submit_on(self.handle, q)
         self.inflight[t] = r
         return t
 

@@ -104,6 +104,61 @@ def test_revolve_counts_are_optimal():
     assert _abi.wf_revolve_forward_steps(5, 0) == -1
 
 
+def _run_schedule(acts, l, s):
+    """Replay a schedule as a state machine (the state in memory, the states
+    held in slots) and return its forward-step count; every action is checked
+    against what the one before it left."""
+    from paper_1808_01995_amd import _abi
+    cur = 0                  # state 0 is in memory and in slot 0 at the start
+    slots = {}
+    advances = 0
+    reversed_steps = []
+    live = 0
+    for kind, at, arg in acts:
+        if kind == _abi.WF_REVOLVE_TAKESHOT:
+            assert at == cur and arg not in slots and 0 <= arg < s
+            slots[arg] = cur
+        elif kind == _abi.WF_REVOLVE_ADVANCE:
+            assert at == cur and arg > at
+            advances += arg - at
+            cur = arg
+        elif kind == _abi.WF_REVOLVE_RESTORE:
+            assert slots.get(arg) == at
+            cur = at
+        elif kind == _abi.WF_REVOLVE_REVERSE:
+            assert at == cur          # the adjoint of step i needs state i
+            reversed_steps.append(at)
+        elif kind == _abi.WF_REVOLVE_FREE:
+            assert arg in slots
+            del slots[arg]
+        else:
+            raise AssertionError(kind)
+        live = max(live, len(slots))
+    assert reversed_steps == list(range(l - 1, -1, -1))   # every step once, last first
+    assert not slots and live <= s
+    return advances, live
+
+
+def test_revolve_schedule_runs_the_optimal_count():
+    """The schedule wf_gradient runs (not the closed form) reverses every
+    step once, holds at most s states, and advances exactly the brute-force
+    optimum T(l, s) for l <= 60 and s <= 6, and at the gradient workload's
+    2000 steps with 20 and 50 states."""
+    from paper_1808_01995_amd import _abi
+    L, S = 60, 6
+    T = _dp_table(L, S)
+    for l in range(1, L + 1):
+        for s in range(1, S + 1):
+            adv, live = _run_schedule(_abi.wf_revolve_schedule(l, s), l, s)
+            assert adv == T[l][s], (l, s, adv)
+            assert live <= min(s, l)
+    for s, t in ((20, 5976), (50, 4622)):
+        adv, live = _run_schedule(_abi.wf_revolve_schedule(2000, s), 2000, s)
+        assert adv == t and live <= s
+    assert _abi.lib.wf_revolve_schedule(0, 3, None, None, None, 0) == _abi.WF_E_ARG
+    assert _abi.lib.wf_revolve_schedule(5, 0, None, None, None, 0) == _abi.WF_E_ARG
+
+
 def test_stream_bandwidth_argument_checks():
     """Argument errors are reported before any device work."""
     import ctypes

@@ -8,7 +8,7 @@ GPU dot test <J dm, r> vs <dm, J^T r> <= 1e-4.
 import numpy as np
 import pytest
 
-from _harness import make_problem, rel_l2
+from _harness import check_record, make_problem, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -40,9 +40,7 @@ def test_born_2d_matches_oracle(k):
     dd, d = prop.born(P.dt, P.nt, P.src_xyz, torch.from_numpy(P.q32).cuda(), torch.from_numpy(dm).cuda(),
                       P.rec_xyz, return_background=True)
     torch.cuda.synchronize()
-    err = rel_l2(dd.cpu().numpy(), _oracle_born(P, dm))
-    print("born 2D order %d rel L2 %.2e" % (k, err))
-    assert err <= 1e-4
+    check_record(dd.cpu().numpy(), _oracle_born(P, dm), label="Born 2D order %d" % k)
     # the background record is wf_forward's, bit for bit
     d2 = prop.forward(P.dt, P.nt, P.src_xyz, torch.from_numpy(P.q32).cuda(), P.rec_xyz)
     torch.cuda.synchronize()
@@ -57,9 +55,7 @@ def test_born_3d_matches_oracle(k):
     dd = prop.born(P.dt, P.nt, P.src_xyz, torch.from_numpy(P.q32).cuda(), torch.from_numpy(dm).cuda(),
                    P.rec_xyz)
     torch.cuda.synchronize()
-    err = rel_l2(dd.cpu().numpy(), _oracle_born(P, dm))
-    print("born 3D order %d rel L2 %.2e" % (k, err))
-    assert err <= 1e-4
+    check_record(dd.cpu().numpy(), _oracle_born(P, dm), label="Born 3D order %d" % k)
 
 
 @pytest.mark.parametrize("ndim", [2, 3])

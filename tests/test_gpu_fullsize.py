@@ -31,7 +31,7 @@ import os
 import numpy as np
 import pytest
 
-from _harness import rel_l2
+from _harness import away_mask, check_field, check_record, point_nodes, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -68,10 +68,8 @@ def test_c3_full_size_window_against_oracle(k):
     d = prop.forward(dt, nt, c.src, q, gold["rec_xyz"]).cpu().numpy()
     prop.close()
     ref = gold["record_so%d" % k]
-    err = rel_l2(d[::4], ref)
-    print("592^3 order %d: window record rel L2 %.3g (max |u| %.3g)" % (k, err, np.abs(ref).max()))
+    check_record(d[::4], ref, label="592^3 order %d window" % k)
     assert np.abs(ref).max() > 1.0
-    assert err <= 1e-4
 
 
 def test_c4_full_size_records_gradient_and_born():
@@ -92,9 +90,12 @@ def test_c4_full_size_records_gradient_and_born():
                        space_order=8, c_ref=2.5)
         assert abs(dt - 0.5 * p.critical_dt(2.5)) <= 1e-12 * dt
         d = p.forward(dt, nt, c.src, q, c.rec)
-        err = rel_l2(d.cpu().numpy()[::4][:, sel], gold["record_" + name])
-        print("280^3 %s model: sampled record rel L2 %.3g" % (name, err))
-        assert err <= 1e-4
+        # 2000 updates: every trace carries an FP32 error of about 1e-5 of
+        # the RMS trace (measured 8.6e-6 on the corner receiver, whose trace
+        # is 0.09 of the RMS), so the relative-to-itself bound applies down
+        # to 0.3 of the RMS trace, the absolute one (3e-5 of it) below
+        check_record(d.cpu().numpy()[::4][:, sel], gold["record_" + name], weak=0.3,
+                     label="280^3 %s model, every 10th receiver in x and y" % name)
         props[name], recs[name] = p, d
     p0 = props["initial"]
     r = (recs["initial"] - recs["true"]).contiguous()
@@ -108,9 +109,11 @@ def test_c4_full_size_records_gradient_and_born():
     rn = band_limited_noise(nt, c.rec.shape[0], dt, float(gs["noise_f0_hz"]), int(gs["noise_seed"]))
     rn = torch.from_numpy(rn.astype(np.float32)).cuda()
     gn = p0.gradient(dt, nt, c.src, q, c.rec, rn, n_checkpoints=-1)
-    err = rel_l2(gn[::st, y, ::st].cpu().numpy(), gs["gradient"])
-    print("280^3 J^T r (shared residual) on the plane y = %d: rel L2 %.3g" % (y, err))
-    assert err <= 1e-3
+    comp = tuple(int(n) + 2 * c.nbl for n in c.shape)
+    nodes = np.vstack([point_nodes(p, c.spacing, c.nbl, comp) for p in (c.src, c.rec)])
+    away = away_mask(comp, nodes, 4)[::st, y, ::st]
+    check_field(gn[::st, y, ::st].cpu().numpy(), gs["gradient"], mask=away,
+                label="280^3 J^T r (shared residual) on the plane y = %d" % y)
     del gn, rn
     for s in (50, 20):
         g = p0.gradient(dt, nt, c.src, q, c.rec, r, n_checkpoints=s)

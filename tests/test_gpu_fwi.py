@@ -11,7 +11,7 @@ bitwise, and every checkpoint count must give the same bits.
 import numpy as np
 import pytest
 
-from _harness import rel_l2
+from _harness import away_mask, check_field, check_record, point_nodes, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -81,12 +81,13 @@ def test_fwi_gradient_matches_oracle(ndim):
         S["grid"], S["m0"].astype(np.float64), S["eta"], S["dt"], S["nt"],
         [(ps, q.astype(np.float64), pr) for ps, q, pr in S["pts"]],
         [d.astype(np.float64) for d in S["d_obs"]])
-    for d, dr in zip(preds, preds_ref):
-        assert rel_l2(d.cpu().numpy(), dr) <= 1e-4
+    for i, (d, dr) in enumerate(zip(preds, preds_ref)):
+        check_record(d.cpu().numpy(), dr, label="fwi %dD shot %d record" % (ndim, i))
     assert abs(phi - phi_ref) <= 1e-3 * phi_ref, (phi, phi_ref)
-    err = rel_l2(g.cpu().numpy(), g_ref)
-    print("fwi %dD: misfit %.6e vs %.6e, gradient rel L2 %.2e" % (ndim, phi, phi_ref, err))
-    assert err <= 1e-3
+    print("fwi %dD: misfit %.6e vs %.6e" % (ndim, phi, phi_ref))
+    nodes = np.vstack([point_nodes(p, S["h"], S["nbl"], S["m0"].shape) for s, q, r in S["shots"] for p in (s, r)])
+    check_field(g.cpu().numpy(), g_ref, mask=away_mask(S["m0"].shape, nodes, S["k"] // 2),
+                label="fwi %dD summed gradient" % ndim)
 
 
 def test_two_solves_equal_three_solve_path():
