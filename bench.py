@@ -613,7 +613,8 @@ def main():
         return
     orders = tuple(int(x) for x in args.orders.split(",") if x)
     if args.rows_only:
-        out = run_rows(torch, args, orders, {})
+        out = {}
+        run_rows(torch, args, orders, out)
         print(json.dumps(out), flush=True)
         return
 
