@@ -195,6 +195,25 @@ wf_status wf_forward(wf_model* model, double dt, int nt,
                      int nrec, const double* rec_xyz, float* rec_out,
                      float* u_save, int save_every, void* stream);
 
+/* wf_forward for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid allocation while they run): the same
+ * modelling with u_save = NULL, the same kernels and the same bits, but the
+ * call's sparse-point tables, fused injection tables and per-step injection
+ * increments are carved from a fixed 32 MiB device scratch that the library
+ * holds per GPU until the process ends, instead of the model's cached
+ * allocations. It calls no device allocation or free. Limits: the tables of
+ * nsrc + nrec points plus nt rows of 4 x (nodes touched by the sources)
+ * floats must fit the 32 MiB (about nt x nsrc x 2^D x 16 bytes for the
+ * increments), else WF_E_BUDGET before any work is queued. The call first
+ * waits for `stream` (earlier calls on it may still read the scratch) and
+ * blocks while it uploads the tables; it is not graph-capturable for that
+ * reason. Calls that overlap on one GPU (on different streams or threads)
+ * share the scratch and race: serialise them. The model itself, created by
+ * wf_model_create, holds the fields and coefficients. */
+wf_status wf_forward_noalloc(wf_model* model, double dt, int nt,
+                             int nsrc, const double* src_xyz, const float* src_wav,
+                             int nrec, const double* rec_xyz, float* rec_out, void* stream);
+
 /* Adjoint x = P_s A(m)^{-T} P_r^T y (eq. Adj): the exact transpose of
  * wf_forward with the same arguments. rec_in device FP32 [nt][nrec] (row 0 is
  * never used), src_out device FP32 [nt][nsrc] (written; row nt-1 is 0). */

@@ -103,6 +103,7 @@ def _load():
         "wf_graph_enable": (I, [I]),
         "wf_model_destroy": (I, [P]),
         "wf_forward": (I, [P, D, I, I, P, P, I, P, P, P, I, P]),
+        "wf_forward_noalloc": (I, [P, D, I, I, P, P, I, P, P, P]),
         "wf_adjoint": (I, [P, D, I, I, P, P, I, P, P, P]),
         "wf_gradient": (I, [P, D, I, I, P, P, I, P, P, P, I, I64, P]),
         "wf_fwi_gradient": (I, [P, D, I, I, ctypes.POINTER(wf_shot), P, P, I, I64, P]),
@@ -138,7 +139,7 @@ lib = _load()
 EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
            "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches", "wf_graph_enable",
            "wf_model_trim",
-           "wf_model_destroy", "wf_forward", "wf_adjoint",
+           "wf_model_destroy", "wf_forward", "wf_forward_noalloc", "wf_adjoint",
            "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_revolve_schedule",
            "wf_profile_enable", "wf_profile_runs_enable", "wf_profile_read", "wf_profile_step_launches",
            "wf_stream_bandwidth", "wf_model_ghost_nonzero", "wf_validate_enable",
@@ -261,6 +262,15 @@ def wf_forward(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, rec_out,
     _check(lib.wf_forward(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None,
                           nr, rp, _ptr(rec_out) if nr else None, _ptr(u_save), int(save_every),
                           _stream(stream)))
+
+
+def wf_forward_noalloc(model, dt: float, nt: int, src_xyz, src_wav, rec_xyz, rec_out, stream=None):
+    """wf_forward without device allocation (tables in the library's fixed
+    per-GPU scratch; raises WaveFDError(WF_E_BUDGET) beyond it)."""
+    ns, sp, _sa = _host(src_xyz)
+    nr, rp, _ra = _host(rec_xyz)
+    _check(lib.wf_forward_noalloc(model, float(dt), int(nt), ns, sp, _ptr(src_wav) if ns else None,
+                                  nr, rp, _ptr(rec_out) if nr else None, _stream(stream)))
 
 
 def wf_adjoint(model, dt: float, nt: int, rec_xyz, rec_in, src_xyz, src_out, stream=None):

@@ -120,7 +120,7 @@ struct Injector {
         vals = series;
         fz = nullptr;
         if (set.nnodes == 0) return WF_OK;
-        if (std::getenv("WAVEFD_NO_FUSED_INJECT") == nullptr) {
+        if (!fused_injection_disabled()) {
             WF_TRY(set.fused(md.L, p, &fz));
             if (!fz->ok) fz = nullptr;
         }
@@ -233,7 +233,7 @@ wf_status launch_graph(Model& md, Model::GraphEntry& e, hipStream_t s) {
 // signature ran eagerly in one of the last calls; else run it eagerly.
 template <class F>
 wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enqueue) {
-    if (!graphs_enabled() || profiling_active() || t_throttle > 0) return enqueue(s);
+    if (!graphs_enabled() || profiling_active() || t_throttle > 0 || thread_scratch_active()) return enqueue(s);
     for (Model::GraphEntry& e : md.graphs)
         if (e.key == key) return launch_graph(md, e, s);
     auto it = std::find(md.seen.begin(), md.seen.end(), key);
@@ -283,6 +283,8 @@ wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enq
 
 void set_graphs_enabled(bool on) { graph_switch().store(on ? 1 : 0); }
 
+bool fused_injection_disabled() { return std::getenv("WAVEFD_NO_FUSED_INJECT") != nullptr; }
+
 void set_thread_throttle(int steps) {
     t_throttle = std::max(0, steps);
     t_thr.count = 0;
@@ -291,13 +293,13 @@ void set_thread_throttle(int steps) {
 
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
-                      hipStream_t s) {
+                      hipStream_t s, DevBuf* inc_buf) {
     const Layout& L = md.L;
     WF_TRY(md.ensure_kap(dt, s));
     StepParams p;
     md.fill_step(p, dt, false);
     Injector inj;
-    WF_TRY(inj.plan(md, src, p, src_wav, nt, md.d_inc[0], s));
+    WF_TRY(inj.plan(md, src, p, src_wav, nt, inc_buf ? *inc_buf : md.d_inc[0], s));
     GraphKey key;
     key.v = {0, (int64_t)nt, bits_of(dt), src.gen, rec.gen, (int64_t)(intptr_t)src_wav,
              (int64_t)(intptr_t)rec_out, (int64_t)(intptr_t)u_save, save_every, p.cx, p.tile,

@@ -125,6 +125,9 @@ std::vector<float> eta_profile(const wf_geom* g, int axis) {
 // ---------------------------------------------------------------------------
 static thread_local Arena* t_arena = nullptr;
 static thread_local hipStream_t t_arena_stream = nullptr;
+static thread_local ScratchRegion* t_scratch = nullptr;
+void set_thread_scratch(ScratchRegion* r) { t_scratch = r; }
+bool thread_scratch_active() { return t_scratch != nullptr; }
 void set_thread_arena(Arena* a, hipStream_t s) {
     t_arena = a;
     t_arena_stream = a ? s : nullptr;
@@ -142,7 +145,7 @@ int64_t device_free_bytes() {
 
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset() {
-    if (ptr) {
+    if (ptr && !external) {
         if (arena) {
             // hipFree waits for the device; the arena does not, so wait for
             // the stream the buffer's work was queued on (a no-op when that
@@ -157,10 +160,22 @@ void DevBuf::reset() {
     bytes = 0;
     arena = nullptr;
     owner = nullptr;
+    external = false;
 }
 wf_status DevBuf::alloc(int64_t nbytes) {
     reset();
     if (nbytes <= 0) return WF_OK;
+    if (t_scratch) {
+        const int64_t off = (t_scratch->used + 255) / 256 * 256;
+        if (off + nbytes > t_scratch->size)
+            return fail(WF_E_BUDGET, "the call needs more than its %lld-byte device scratch (%lld bytes in use, "
+                        "%lld more requested)", (long long)t_scratch->size, (long long)off, (long long)nbytes);
+        ptr = t_scratch->base + off;
+        bytes = nbytes;
+        external = true;
+        t_scratch->used = off + nbytes;
+        return WF_OK;
+    }
     if (t_arena) {
         void* q = arena_alloc(t_arena, nbytes);
         if (!q) return fail(WF_E_BUDGET, "device arena exhausted (%lld bytes requested)", (long long)nbytes);

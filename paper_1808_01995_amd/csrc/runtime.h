@@ -39,11 +39,24 @@ int64_t arena_largest_free(Arena* a);
 // for it, so that no queued kernel still uses memory the arena hands out again.
 void set_thread_arena(Arena* a, hipStream_t s = nullptr);
 
+// Caller-provided device memory handed out front to back (the static scratch
+// of the no-allocation entry point): while set on a thread, DevBuf
+// allocations made by that thread are carved from it and never freed on
+// their own; a carve beyond `size` fails with WF_E_BUDGET.
+struct ScratchRegion {
+    char* base = nullptr;
+    int64_t size = 0;
+    int64_t used = 0;
+};
+void set_thread_scratch(ScratchRegion* r);
+bool thread_scratch_active();
+
 // Owned device allocation.
 struct DevBuf {
     void* ptr = nullptr;
     int64_t bytes = 0;
     Arena* arena = nullptr;
+    bool external = false;         // carved from a ScratchRegion: nothing to free
     hipStream_t owner = nullptr;   // arena buffers: the stream to wait for before freeing
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
@@ -223,9 +236,13 @@ void set_thread_throttle(int steps);
 // initially on when WAVEFD_VALIDATE=1)
 bool validation_enabled();
 void set_validation(bool on);
+// inc_buf: the buffer of the per-step injection increments (default: the
+// model's own, grown as needed)
 wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
                       const PointSet& rec, float* rec_out, float* u_save, int save_every,
-                      hipStream_t s);
+                      hipStream_t s, DevBuf* inc_buf = nullptr);
+// WAVEFD_NO_FUSED_INJECT set: sources go through the separate injection kernel
+bool fused_injection_disabled();
 wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const float* rec_in,
                       const PointSet& src, float* src_out, hipStream_t s);
 // Adjoint-state gradient (dense grad_out, overwritten). With d_obs (device
