@@ -90,10 +90,11 @@ def test_c4_full_size_records_gradient_and_born():
                        space_order=8, c_ref=2.5)
         assert abs(dt - 0.5 * p.critical_dt(2.5)) <= 1e-12 * dt
         d = p.forward(dt, nt, c.src, q, c.rec)
-        # 2000 updates: every trace carries an FP32 error of about 1e-5 of
-        # the RMS trace (measured 8.6e-6 on the corner receiver, whose trace
-        # is 0.09 of the RMS), so the relative-to-itself bound applies down
-        # to 0.3 of the RMS trace, the absolute one (3e-5 of it) below
+        # 2000 updates: every trace carries an FP32 error of about the
+        # record's rel. L2 times the RMS trace (measured 8.6e-6 of the RMS on
+        # the corner receiver, whose trace is 0.09 of the RMS), so the
+        # relative-to-itself bound applies down to 0.3 of the RMS trace and
+        # the absolute one (3e-5 of it) below
         check_record(d.cpu().numpy()[::4][:, sel], gold["record_" + name], weak=0.3,
                      label="280^3 %s model, every 10th receiver in x and y" % name)
         props[name], recs[name] = p, d

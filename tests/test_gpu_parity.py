@@ -231,7 +231,11 @@ def test_c2_full_size_against_stored_oracle_record():
     q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
     d = prop.forward(dt, c.nt, c.src, q, c.rec).cpu().numpy()
     sel = gold["receiver_index"]
-    check_record(d[:, sel], gold["record"], label="C2 full size, every 8th receiver in x and y")
+    # 1000 updates: every trace carries an FP32 error of about the record's
+    # rel. L2 times the RMS trace (measured up to 1.1 x 1.05e-5 on traces at
+    # 0.1 of the RMS), so the relative-to-itself bound applies down to 0.3
+    # of the RMS trace and the absolute one (3e-5 of it) below
+    check_record(d[:, sel], gold["record"], weak=0.3, label="C2 full size, every 8th receiver in x and y")
     prop.close()
 
 
