@@ -55,6 +55,10 @@ __device__ __forceinline__ float4 ld4s(const float* p) {
 #ifndef WF_NT_OUT
 #define WF_NT_OUT WF_STREAM_NT
 #endif
+// Planes of lookahead of the streamed operands and halos (1 or 2).
+#ifndef WF_LA
+#define WF_LA 1
+#endif
 __device__ __forceinline__ void st4o(float* p, const float4& v) {
 #if WF_NT_OUT
     f4v t;
@@ -86,6 +90,25 @@ __device__ __forceinline__ void set_comp(float4& v, int i, float s) {
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int per = (nb + 7) >> 3;
     return (b & 7) * per + (b >> 3);
+}
+
+// Planes of lookahead of the halo loads of the step kernel: M + PF (the
+// distance at which the neighbouring blocks load the same rows into their
+// rings) where the registers allow it, else the largest divisor of the ring
+// length that keeps the kernel at its occupancy. WF_HL overrides it.
+#ifndef WF_HL
+#define WF_HL 0
+#endif
+__host__ __device__ constexpr int halo_lookahead(int M, int PF, bool d3, int mode) {
+    const int nq = 2 * M + 1 + PF;
+    // the imaging and source modes hold more operands per plane
+    const bool plain = mode == 0;
+    int cap = M + PF;
+    if (d3 && plain && M > 4) cap = M <= 6 ? 2 : 3;
+    if (d3 && !plain && M > 3) cap = M <= 6 ? 2 : 1;
+    if (WF_HL > 0) cap = WF_HL;
+    while (cap > 1 && nq % cap != 0) --cap;   // the largest divisor of the ring length up to cap
+    return cap;
 }
 
 // One point's update, given its Laplacian.
@@ -227,26 +250,47 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
     for (int s = 0; s < 2 * M + PF; ++s) ring[s] = ld4(p.cur + (int64_t)(xb - M + s) * sx + col);
     ring[NQ - 1] = zero4();
 
-    float4 uo_n, kp_n, uf_n = zero4(), gr_n = zero4();
-    float4 hy_n[JY], hz_n[JZ];
-    float ex_n;
-    auto load_next = [&](int xx) {
+    // old, kappa and the imaging/source operands of plane x are loaded LA
+    // planes before x is computed, into register slot x % LA; the y/z halo
+    // rows of plane x, HL planes before, into halo slot x % HL. With HL =
+    // M + PF a block reads its neighbours' rows of a plane in the same
+    // iteration as those neighbours load them into their own rings (blocks
+    // sharing halos run side by side on one XCD), so the halo reads find the
+    // rows in L2 rather than fetching them again from HBM. The ring length
+    // NQ is a multiple of LA and HL, so every unrolled plane's slots are
+    // compile-time constants.
+    constexpr int LA = WF_LA;
+    constexpr int HL = halo_lookahead(M, PF, D3, MODE);
+    static_assert(NQ % LA == 0, "lookahead must divide the ring length");
+    static_assert(NQ % HL == 0, "halo lookahead must divide the ring length");
+    float4 uo_q[LA], kp_q[LA], uf_q[LA], gr_q[LA];
+    float4 hy_q[HL][JY], hz_q[HL][JZ];
+    float ex_q[LA];
+    auto load_ahead = [&](int sl, int xx) {
         const int64_t b = (int64_t)xx * sx;
-        ex_n = p.etax[min(xx, p.nx - 1)];
-        uo_n = ld4s(p.old + b + col);
-        kp_n = ld4s(p.kap + b + col);
+        ex_q[sl] = p.etax[min(xx, p.nx - 1)];
+        uo_q[sl] = ld4s(p.old + b + col);
+        kp_q[sl] = ld4s(p.kap + b + col);
+        uf_q[sl] = zero4();
+        gr_q[sl] = zero4();
         if (IMG) {
-            uf_n = ld4s(p.ufwd + b + col);
-            gr_n = ld4s(p.grad + b + col);
+            uf_q[sl] = ld4s(p.ufwd + b + col);
+            gr_q[sl] = ld4s(p.grad + b + col);
         }
-        if (BSRC) uf_n = ld4s(p.ufwd + b + col);
-        if (VSRC) uf_n = ld4s(p.vsrc + b + col);
-#pragma unroll
-        for (int j = 0; j < JY; ++j) hy_n[j] = ld4(p.cur + b + hy_c[j]);
-#pragma unroll
-        for (int j = 0; j < JZ; ++j) hz_n[j] = ld4(p.cur + b + hz_c[j]);
+        if (BSRC) uf_q[sl] = ld4s(p.ufwd + b + col);
+        if (VSRC) uf_q[sl] = ld4s(p.vsrc + b + col);
     };
-    load_next(xb);
+    auto load_halo = [&](int sl, int xx) {
+        const int64_t b = (int64_t)xx * sx;
+#pragma unroll
+        for (int j = 0; j < JY; ++j) hy_q[sl][j] = ld4(p.cur + b + hy_c[j]);
+#pragma unroll
+        for (int j = 0; j < JZ; ++j) hz_q[sl][j] = ld4(p.cur + b + hz_c[j]);
+    };
+#pragma unroll
+    for (int i = 0; i < HL; ++i) load_halo(i, xb + i);
+#pragma unroll
+    for (int i = 0; i < LA; ++i) load_ahead(i, xb + i);
 
     // this block's share of the receivers: interpolate cur (which the step
     // only reads); issued after the prologue loads so that the gather's
@@ -274,15 +318,17 @@ __device__ __forceinline__ void step_body(const StepParams& p, const int bidx) {
         for (int ph = 0; ph < NQ; ++ph) {
             const int x = xg + ph;
             if (x < xe) {   // uniform; a guarded body keeps the loop fully unrollable
-                // this plane's operands, loaded one plane ago
-                const float4 uo = uo_n, kp = kp_n, uf = uf_n, gr = gr_n;
-                const float ex = ex_n;
+                // this plane's operands, loaded LA planes ago
+                const int sl = ph % LA, hs = ph % HL;
+                const float4 uo = uo_q[sl], kp = kp_q[sl], uf = uf_q[sl], gr = gr_q[sl];
+                const float ex = ex_q[sl];
                 float4 hy[JY], hz[JZ];
 #pragma unroll
-                for (int j = 0; j < JY; ++j) hy[j] = hy_n[j];
+                for (int j = 0; j < JY; ++j) hy[j] = hy_q[hs][j];
 #pragma unroll
-                for (int j = 0; j < JZ; ++j) hz[j] = hz_n[j];
-                load_next(x + 1);   // plane nx at the end is a ghost plane
+                for (int j = 0; j < JZ; ++j) hz[j] = hz_q[hs][j];
+                load_halo(hs, x + HL);    // planes from nx on are ghost planes
+                load_ahead(sl, x + LA);
                 ring[(ph + 2 * M + PF) % NQ] = ld4(p.cur + (int64_t)(x + M + PF) * sx + col);
                 const float4 c = ring[(ph + M) % NQ];
                 float* L = lds + (x & 1) * LBUF;
@@ -726,7 +772,14 @@ void step_plan(StepParams& p, int ndim, int half, int mode, int cx_request, int 
     if (cx <= 0) {
         // Chunks along x trade parallelism against the 2M + PF planes every
         // chunk re-reads to fill its register ring. Cost model per resident
-        // round of blocks: (planes + warm-up) / occupancy, times the rounds.
+        // round of blocks: (planes + warm-up) / occupancy, times the rounds,
+        // plus kRoundPlanes planes per round beyond the first: blocks of a
+        // later round start out of step with their neighbours (whose rows
+        // they read as halos) and with the other x positions in flight (the
+        // same walk with no stencil at 592^3 took 615 us in one round of 740
+        // blocks and 645 us in two rounds of 1480; the step kernel 663 and
+        // 680 us at order 8).
+        constexpr double kRoundPlanes = 8.0;
         const int cap = step_capacity(ndim, half, tile, mode);
         const int warm = 2 * half + 1;
         double best = 1e300;
@@ -737,7 +790,7 @@ void step_plan(StepParams& p, int ndim, int half, int mode, int cx_request, int 
             const double blocks = (double)tiles * n;
             const double rounds = std::ceil(blocks / cap);
             const double fill = std::min(1.0, blocks / cap);
-            const double cost = rounds * (c + warm) / fill;
+            const double cost = rounds * (c + warm) / fill + (rounds - 1) * kRoundPlanes;
             if (cost < best * 0.999) {
                 best = cost;
                 best_n = n;
