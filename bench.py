@@ -161,6 +161,35 @@ def graph_c1(torch, shots=20):
     return res
 
 
+def c1_batch(torch, counts=(1, 8, 32), steps=500):
+    """C1-size forward shots (101^2 physical + 20-node layer = 141^2, order 4,
+    500 updates, 101 receivers at 20 m, smooth random velocity) through the
+    serving engine: N requests submitted together share every batched step
+    launch; wall time from submission to the last completion, per grid and
+    update, against the same shots one at a time on the plain propagator
+    (one launch per update)."""
+    from paper_1808_01995_amd.serve import Server, build_request, run_one_shot_baseline, run_stream
+    specs = [{"ndim": 2, "n": 101, "space_order": 4, "steps": steps, "kind": "forward", "seed": 300 + i}
+             for i in range(max(counts))]
+    reqs = [build_request(s, nbl=20) for s in specs]
+    torch.cuda.synchronize()
+    base = run_one_shot_baseline(reqs[:8], 4 << 30)
+    one = base["seconds"] / (8 * steps) * 1e6
+    srv = Server(hbm_budget_bytes=4 << 30, max_slots=64)
+    run_stream(srv, reqs[:2])   # warm-up
+    rows = []
+    for n in counts:
+        st = run_stream(srv, reqs[:n])
+        rows.append({"grids": n, "makespan_ms": round(st["makespan_s"] * 1e3, 2),
+                     "us_per_grid_update": round(st["makespan_s"] * 1e6 / (n * steps), 3),
+                     "failed": st["failed"]})
+        log("c1 batch %d: %s" % (n, rows[-1]))
+    srv.close()
+    return {"workload": "141^2 computational (101^2 + 20-node layer), order 4, %d updates, 101 receivers; "
+                        "engine makespan (model set-up included) per grid-update" % steps,
+            "one_at_a_time_us_per_update": round(one, 3), "engine": rows}
+
+
 def large_2d(torch, n=8192, orders=(4, 8, 12), steps=300):
     """Large 2D grids: n^2 physical + 40-node layer, v = 2 km/s, one source,
     256 receivers at 20 m; GPts/s and the step kernel's algorithmic bandwidth
@@ -437,11 +466,11 @@ def fwi_multishot(torch, steps=2000, iters=3):
                     "allocates the model's gradient workspace (store-all: 2001 fields, 176 GB)"}
 
 
-def serving_c5(torch, n_requests=32, seed=5):
-    """The serving stream at full size (the first `n_requests` of the seeded
-    mix: 2D 256^2-2048^2 or 3D 128^3-384^3 physical, orders 4/8/12, 500-2000
-    updates, 1 in 4 a gradient): one-shot-per-launch baseline mu_0, saturated
-    throughput, Poisson arrivals at 0.5/0.8/1.2 mu_0."""
+def serving_c5(torch, n_requests=256, seed=5):
+    """The serving stream at full size (the seeded mix of 256 requests, or its
+    first `n_requests`: 2D 256^2-2048^2 or 3D 128^3-384^3 physical, orders
+    4/8/12, 500-2000 updates, 1 in 4 a gradient): one-shot-per-launch baseline
+    mu_0, saturated throughput, Poisson arrivals at 0.5/0.8/1.2 mu_0."""
     from paper_1808_01995_amd.serve import (GRADIENT_SHARE, Server, build_request, run_one_shot_baseline,
                                             run_stream)
     from synthetic import serving_requests
@@ -543,6 +572,7 @@ def run_rows(torch, args, orders, out):
         rows = {"c1", "2d", "c3", "slab", "c4", "born", "fwi", "serve"}
     if "c1" in rows:
         out["c1_graph"] = graph_c1(torch)
+        out["c1_batch"] = c1_batch(torch)
     if "2d" in rows:
         out["large_2d"] = large_2d(torch)
     if "c3" in rows:
@@ -569,9 +599,9 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
     ap.add_argument("--rows", default="",
                     help="comma list of further rows to measure: c1,2d,c3,slab,c4,born,fwi,serve (or all)")
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the full-size serving stream measured with the headline "
-                         "(0: skip; 256 is the whole seeded mix)")
+                         "(default: the whole seeded mix of 256; 0 skips it)")
     ap.add_argument("--updates", type=int, default=None,
                     help="shorter shots (profiling runs only; the benchmark uses 1000): the headline "
                          "shot and, with --rows c3, the sweep's shots")

@@ -11,7 +11,10 @@
 //   time steps per iteration, one k_step_batch launch per step per (dimension,
 //   order, tile) group; requests join and leave between iterations, so
 //   arrivals are admitted while others are on the GPU and their steps share
-//   launches. The arithmetic of every grid is independent of the batch.
+//   launches. Two iterations are in flight: arrivals are set up on a second
+//   stream and the next iteration is enqueued while the device runs the
+//   current one, so the device does not wait for the host between them. The
+//   arithmetic of every grid is independent of the batch.
 // * Other requests (large grids, gradients) run on worker threads, each with
 //   its own non-blocking stream, concurrently with the batch. A free worker
 //   takes the admitted request with the earliest expected completion (arrival
@@ -383,15 +386,52 @@ void wf_engine::worker() {
 
 void wf_engine::batcher() {
     (void)hipSetDevice(device);
-    hipStream_t s = nullptr;
+    // launches of the batched steps go to `s`; newly admitted grids are set
+    // up on `s_setup` meanwhile, and the launches that first include them
+    // wait for that set-up on the device
+    hipStream_t s = nullptr, s_setup = nullptr;
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    set_thread_arena(arena, s);
-    BatchJob* host_tab = nullptr;
-    int cap_tab = 0;
-    DevBuf dev_tab;
+    (void)hipStreamCreateWithFlags(&s_setup, hipStreamNonBlocking);
+    hipEvent_t setup_ev = nullptr;
+    (void)hipEventCreateWithFlags(&setup_ev, hipEventDisableTiming);
+    // grids are retired only after the iteration that last used them has run
+    // (an event), so freeing their buffers waits for the set-up stream alone
+    set_thread_arena(arena, s_setup);
+    // Two iterations in flight: while the device runs one, the host sets up
+    // arrivals and enqueues the next; each has its own job tables and an
+    // event, and the grids that finished in it are completed when its event
+    // has fired.
+    struct Slot {
+        BatchJob* host = nullptr;
+        int cap = 0;
+        DevBuf dev;
+        hipEvent_t ev = nullptr;
+        bool armed = false;
+        std::vector<EJob*> retiring;
+    };
+    Slot slot[2];
+    for (Slot& sl : slot) (void)hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    int cur = 0;
+    auto drain = [&](Slot& sl) {
+        if (!sl.armed) return;
+        const wf_status st = hip_check(hipEventSynchronize(sl.ev), "batched iteration");
+        sl.armed = false;
+        std::vector<EJob*> done_jobs;
+        done_jobs.swap(sl.retiring);
+        for (EJob* j : done_jobs) {
+            if (st != WF_OK && j->st == WF_OK) j->st = st;
+            delete j->md;
+            j->md = nullptr;
+            complete(j);
+        }
+    };
     std::vector<EJob*> active;
     for (;;) {
         std::vector<EJob*> fresh;
+        if (active.empty()) {
+            drain(slot[0]);
+            drain(slot[1]);
+        }
         {
             std::unique_lock<std::mutex> lk(mu);
             if (active.empty())
@@ -404,21 +444,24 @@ void wf_engine::batcher() {
         }
         size_t fresh_in_active = 0;   // fresh grids already moved to `active`
         try {
-        // set up newly admitted grids (their first step joins this iteration)
+        // set up newly admitted grids on the set-up stream (their first step
+        // joins this iteration)
         for (EJob* j : fresh) {
             const wf_request& r = j->rq;
             j->md = new (std::nothrow) Model();
-            wf_status st = j->md ? j->wait_inputs(s) : fail(WF_E_NOMEM, "host allocation");
-            if (st == WF_OK) st = j->md->init(&r.geom, r.m_dev, s);
+            wf_status st = j->md ? j->wait_inputs(s_setup) : fail(WF_E_NOMEM, "host allocation");
+            if (st == WF_OK) st = j->md->init(&r.geom, r.m_dev, s_setup);
             if (st == WF_OK) st = j->md->check_dt(r.dt);
             if (st == WF_OK) st = j->md->points(r.nsrc, j->src.data(), &j->ps_src);
             if (st == WF_OK) st = j->md->points(r.nrec, j->rec.data(), &j->ps_rec);
             if (st == WF_OK)
-                st = batch_forward_begin(*j->md, r.dt, r.nt, *j->ps_src, r.src_wav, *j->ps_rec, r.rec_out, s, j->bf);
+                st = batch_forward_begin(*j->md, r.dt, r.nt, *j->ps_src, r.src_wav, *j->ps_rec, r.rec_out, s_setup,
+                                         j->bf);
             if (st == WF_E_STATE) {
                 // not batchable (too many sources in one block): run it alone
-                st = run_forward(*j->md, r.dt, r.nt, *j->ps_src, r.src_wav, *j->ps_rec, r.rec_out, nullptr, 1, s);
-                if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+                st = run_forward(*j->md, r.dt, r.nt, *j->ps_src, r.src_wav, *j->ps_rec, r.rec_out, nullptr, 1,
+                                 s_setup);
+                if (st == WF_OK) st = hip_check(hipStreamSynchronize(s_setup), "sync");
                 j->bf.n = r.nt - 1;
                 j->bf.nt = r.nt;
                 j->bf.rec = nullptr;
@@ -427,24 +470,36 @@ void wf_engine::batcher() {
             active.push_back(j);
             ++fresh_in_active;
         }
-        // one iteration: kBatchSteps steps of every active grid
+        if (!fresh.empty()) {
+            wf_status st = hip_check(hipEventRecord(setup_ev, s_setup), "event");
+            if (st == WF_OK) st = hip_check(hipStreamWaitEvent(s, setup_ev, 0), "wait for set-up");
+            if (st != WF_OK)
+                for (EJob* j : fresh) j->st = st;
+        }
+        // one iteration: kBatchSteps steps of every active grid, one launch
+        // per step per (dimension, order, tile) group
         std::map<std::tuple<int, int, int>, std::vector<EJob*>> groups;
         for (EJob* j : active)
             if (j->st == WF_OK && j->bf.n < j->bf.nt - 1)
                 groups[std::make_tuple(j->md->geom.ndim, j->md->half, j->bf.p.tile)].push_back(j);
         int ntab = 0;
         for (auto& g : groups) ntab += (int)g.second.size();
+        Slot& sl = slot[cur];
+        drain(sl);   // its tables and its finished grids are free now
         wf_status st = WF_OK;
         if (ntab > 0) {
-            if (ntab > cap_tab) {
-                if (host_tab) (void)hipHostFree(host_tab);
-                cap_tab = std::max(ntab, 2 * cap_tab);
-                if (hipHostMalloc(reinterpret_cast<void**>(&host_tab), sizeof(BatchJob) * cap_tab) != hipSuccess) {
-                    host_tab = nullptr;
-                    cap_tab = 0;
+            if (ntab > sl.cap) {
+                if (sl.host) (void)hipHostFree(sl.host);
+                sl.host = nullptr;
+                sl.cap = 0;
+                const int cap = std::max(ntab, 64);
+                if (hipHostMalloc(reinterpret_cast<void**>(&sl.host), sizeof(BatchJob) * cap) != hipSuccess) {
+                    sl.host = nullptr;
                     st = fail(WF_E_NOMEM, "pinned host table");
+                } else {
+                    sl.cap = cap;
+                    st = sl.dev.alloc((int64_t)sizeof(BatchJob) * cap);
                 }
-                if (st == WF_OK) st = dev_tab.alloc((int64_t)sizeof(BatchJob) * cap_tab);
             }
             struct G { int off, n, total, ndim, half, tile; };
             std::vector<G> gl;
@@ -453,7 +508,7 @@ void wf_engine::batcher() {
                 if (st != WF_OK) break;   // no table to fill
                 int begin = 0;
                 for (size_t q = 0; q < g.second.size(); ++q) {
-                    host_tab[off + (int)q] = batch_forward_job(g.second[q]->bf, kBatchSteps, begin);
+                    sl.host[off + (int)q] = batch_forward_job(g.second[q]->bf, kBatchSteps, begin);
                     begin += g.second[q]->bf.nblk;
                 }
                 gl.push_back({off, (int)g.second.size(), begin, std::get<0>(g.first), std::get<1>(g.first),
@@ -461,13 +516,12 @@ void wf_engine::batcher() {
                 off += (int)g.second.size();
             }
             if (st == WF_OK)
-                st = hip_check(hipMemcpyAsync(dev_tab.ptr, host_tab, sizeof(BatchJob) * ntab,
-                                              hipMemcpyHostToDevice, s), "batch table");
+                st = hip_check(hipMemcpyAsync(sl.dev.ptr, sl.host, sizeof(BatchJob) * ntab, hipMemcpyHostToDevice, s),
+                               "batch table");
             for (int k = 0; k < kBatchSteps && st == WF_OK; ++k)
                 for (const G& g : gl)
-                    st = hip_check(launch_step_batch(dev_tab.as<BatchJob>() + g.off, g.n, g.total, g.ndim,
-                                                     g.half, g.tile, k, s), "batched step");
-            if (st == WF_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+                    st = hip_check(launch_step_batch(sl.dev.as<BatchJob>() + g.off, g.n, g.total, g.ndim, g.half,
+                                                     g.tile, k, s), "batched step");
             for (auto& g : groups)
                 for (EJob* j : g.second) {
                     const int steps = std::max(0, std::min(kBatchSteps, j->bf.nt - 1 - j->bf.n));
@@ -475,7 +529,8 @@ void wf_engine::batcher() {
                     if (st != WF_OK) j->st = st;
                 }
         }
-        // retire finished grids
+        // grids done after this iteration: their last record row, then they
+        // retire with the iteration's event
         std::vector<EJob*> keep;
         keep.reserve(active.size());   // no allocation once grids start to retire
         for (EJob*& j : active) {
@@ -483,24 +538,40 @@ void wf_engine::batcher() {
                 keep.push_back(j);
                 continue;
             }
-            if (j->st == WF_OK && j->bf.rec) {
-                j->st = batch_forward_finish(j->bf, s);
-                if (j->st == WF_OK) j->st = hip_check(hipStreamSynchronize(s), "sync");
-            }
-            delete j->md;
-            j->md = nullptr;
-            EJob* done_job = j;
-            j = nullptr;   // retired: the error path below must not touch it
-            complete(done_job);
+            if (j->st == WF_OK && j->bf.rec) j->st = batch_forward_finish(j->bf, s);
+            sl.retiring.push_back(j);
+            j = nullptr;   // handed to the slot: the error path below must not touch it
         }
         active.swap(keep);
+        const wf_status se = hip_check(hipEventRecord(sl.ev, s), "event");
+        if (se == WF_OK) {
+            sl.armed = true;
+        } else {
+            // no event: wait for the stream instead and retire at once
+            (void)hipStreamSynchronize(s);
+            for (EJob* j : sl.retiring) j->st = se;
+            std::vector<EJob*> done_jobs;
+            done_jobs.swap(sl.retiring);
+            for (EJob* j : done_jobs) {
+                delete j->md;
+                j->md = nullptr;
+                complete(j);
+            }
+        }
+        cur ^= 1;
         } catch (...) {
             // a host allocation failed: every grid in the batch fails (after
             // the launches already issued have finished), the slots are freed
             (void)hipStreamSynchronize(s);
+            (void)hipStreamSynchronize(s_setup);
             for (size_t i = fresh_in_active; i < fresh.size(); ++i) active.push_back(fresh[i]);
+            for (Slot& q : slot) {
+                for (EJob* j : q.retiring) active.push_back(j);
+                q.retiring.clear();
+                q.armed = false;
+            }
             for (EJob* j : active) {
-                if (!j) continue;   // already retired
+                if (!j) continue;   // already handed over
                 delete j->md;
                 j->md = nullptr;
                 j->st = fail(WF_E_NOMEM, "host allocation failed while batching");
@@ -509,9 +580,16 @@ void wf_engine::batcher() {
             active.clear();
         }
     }
-    if (host_tab) (void)hipHostFree(host_tab);
-    dev_tab.reset();
+    drain(slot[0]);
+    drain(slot[1]);
+    for (Slot& sl : slot) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.dev.reset();
+        (void)hipEventDestroy(sl.ev);
+    }
+    (void)hipEventDestroy(setup_ev);
     (void)hipStreamDestroy(s);
+    (void)hipStreamDestroy(s_setup);
     set_thread_arena(nullptr);
 }
 
