@@ -161,13 +161,16 @@ def graph_c1(torch, shots=20):
     return res
 
 
-def c1_batch(torch, counts=(1, 8, 32), steps=500):
+def c1_batch(torch, counts=(1, 8, 32, 256), steps=500):
     """C1-size forward shots (101^2 physical + 20-node layer = 141^2, order 4,
     500 updates, 101 receivers at 20 m, smooth random velocity) through the
-    serving engine: N requests submitted together share every batched step
-    launch; wall time from submission to the last completion, per grid and
+    serving engine, N requests submitted together: on resident teams (each
+    shot's fields held in one work-group's LDS for the whole shot) and, with
+    those switched off, on batched step launches (all grids share every step
+    launch); wall time from submission to the last completion, per grid and
     update, against the same shots one at a time on the plain propagator
     (one launch per update)."""
+    import os
     from paper_1808_01995_amd.serve import Server, build_request, run_one_shot_baseline, run_stream
     specs = [{"ndim": 2, "n": 101, "space_order": 4, "steps": steps, "kind": "forward", "seed": 300 + i}
              for i in range(max(counts))]
@@ -175,19 +178,26 @@ def c1_batch(torch, counts=(1, 8, 32), steps=500):
     torch.cuda.synchronize()
     base = run_one_shot_baseline(reqs[:8], 4 << 30)
     one = base["seconds"] / (8 * steps) * 1e6
-    srv = Server(hbm_budget_bytes=4 << 30, max_slots=64)
-    run_stream(srv, reqs[:2])   # warm-up
-    rows = []
-    for n in counts:
-        st = run_stream(srv, reqs[:n])
-        rows.append({"grids": n, "makespan_ms": round(st["makespan_s"] * 1e3, 2),
-                     "us_per_grid_update": round(st["makespan_s"] * 1e6 / (n * steps), 3),
-                     "failed": st["failed"]})
-        log("c1 batch %d: %s" % (n, rows[-1]))
-    srv.close()
+    paths = {}
+    for label, teams in (("resident_teams", "1"), ("batched_launches", "0")):
+        os.environ["WAVEFD_TEAMS"] = teams
+        try:
+            srv = Server(hbm_budget_bytes=8 << 30, max_slots=max(counts))
+        finally:
+            del os.environ["WAVEFD_TEAMS"]
+        run_stream(srv, reqs[:2])   # warm-up
+        rows = []
+        for n in counts:
+            st = run_stream(srv, reqs[:n])
+            rows.append({"grids": n, "makespan_ms": round(st["makespan_s"] * 1e3, 2),
+                         "us_per_grid_update": round(st["makespan_s"] * 1e6 / (n * steps), 3),
+                         "failed": st["failed"]})
+            log("c1 %s %d: %s" % (label, n, rows[-1]))
+        paths[label] = {"rows": rows, "requests_by_path": srv.paths()}
+        srv.close()
     return {"workload": "141^2 computational (101^2 + 20-node layer), order 4, %d updates, 101 receivers; "
                         "engine makespan (model set-up included) per grid-update" % steps,
-            "one_at_a_time_us_per_update": round(one, 3), "engine": rows}
+            "one_at_a_time_us_per_update": round(one, 3), "engine": paths}
 
 
 def large_2d(torch, n=8192, orders=(4, 8, 12), steps=300):

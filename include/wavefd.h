@@ -448,6 +448,19 @@ wf_status wf_engine_poll(wf_engine* engine, uint64_t* done_tickets, wf_status* d
 wf_status wf_engine_stats(const wf_engine* engine, int64_t* queued, int64_t* running,
                           int64_t* completed, int64_t* bytes_in_use);
 
+/* Completed requests by the path that ran them (any pointer may be NULL):
+ * forward shots whose two wavefields fit one work-group's LDS (z padded to
+ * 4, at most 40 640 floats for both: e.g. 141 x 141 in 2D, 26^3 in 3D) run
+ * as resident teams, each work-group of a launch stepping a whole request
+ * in LDS with only work-group barriers (requests of one dimension and order
+ * that are set up together share a launch; up to 4 launches run at once);
+ * other forward shots of at most 5 M nodes share batched step launches; the
+ * rest, and every gradient, run on worker streams. Resident teams are on by
+ * default; WAVEFD_TEAMS=0 in the environment at engine creation sends their
+ * requests to the batched launches instead. Results are the same bits on
+ * every path. WF_E_ARG if engine is NULL. */
+wf_status wf_engine_paths(const wf_engine* engine, int64_t* teams, int64_t* batched, int64_t* workers);
+
 /* Wait for every request, then free the engine. */
 wf_status wf_engine_destroy(wf_engine* engine);
 

@@ -124,6 +124,7 @@ def _load():
         "wf_engine_poll": (I, [P, P, P, I, P, I]),
         "wf_engine_request_bytes": (I, [ctypes.POINTER(wf_request), I64, P]),
         "wf_engine_stats": (I, [P, P, P, P, P]),
+        "wf_engine_paths": (I, [P, P, P, P]),
         "wf_engine_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
@@ -144,7 +145,7 @@ EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf
            "wf_profile_enable", "wf_profile_runs_enable", "wf_profile_read", "wf_profile_step_launches",
            "wf_stream_bandwidth", "wf_model_ghost_nonzero", "wf_validate_enable",
            "wf_engine_create", "wf_engine_submit", "wf_engine_submit_on", "wf_engine_request_bytes",
-           "wf_engine_poll", "wf_engine_stats", "wf_engine_destroy")
+           "wf_engine_poll", "wf_engine_stats", "wf_engine_paths", "wf_engine_destroy")
 
 
 def _check(st: int):
@@ -439,6 +440,13 @@ def wf_engine_stats(engine):
     q, r, c, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib.wf_engine_stats(engine, ctypes.byref(q), ctypes.byref(r), ctypes.byref(c), ctypes.byref(b)))
     return {"queued": q.value, "running": r.value, "completed": c.value, "bytes_in_use": b.value}
+
+
+def wf_engine_paths(engine):
+    """Completed requests per path: resident teams, batched launches, workers."""
+    t, b, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.wf_engine_paths(engine, ctypes.byref(t), ctypes.byref(b), ctypes.byref(w)))
+    return {"teams": t.value, "batched": b.value, "workers": w.value}
 
 
 def wf_engine_destroy(engine):

@@ -151,6 +151,8 @@ struct EJob {
     wf_request rq{};
     std::vector<double> src, rec;
     bool small = false;
+    bool tiny = false;      // forward shot whose two fields fit one work-group's LDS (resident team)
+    int path = 2;           // where it ran: 0 resident team, 1 batched launches, 2 a worker
     bool heavy = false;     // grid above kSmallPoints nodes: runs alone among the workers' jobs
     bool counted = false;   // counted in heavy_running while it runs
     double due = 0.0;       // arrival (s, steady clock) + estimated run time alone
@@ -161,6 +163,7 @@ struct EJob {
     BatchFwd bf;
     const PointSet* ps_src = nullptr;
     const PointSet* ps_rec = nullptr;
+    DevBuf inc;                   // resident team: the source increments of every step
     hipEvent_t ready = nullptr;   // recorded on the submitter's stream: the inputs are complete
     ~EJob() {
         if (ready) (void)hipEventDestroy(ready);
@@ -232,9 +235,12 @@ struct wf_engine {
     std::deque<EJob*> pending;
     std::deque<EJob*> small_ready;
     std::deque<EJob*> large_ready;
+    std::deque<EJob*> tiny_ready;
+    bool teams_on = true;       // tiny forward shots go to resident teams
     std::deque<std::pair<uint64_t, wf_status>> done;
     int64_t reserved = 0;
     int running = 0;
+    int64_t served[3] = {0, 0, 0};   // completed requests by path: resident teams, batched launches, workers
     int heavy_running = 0;      // heavy requests on the workers (0 or 1)
     int64_t completed = 0;
     bool stop = false;
@@ -248,13 +254,23 @@ struct wf_engine {
             pending.pop_front();
             reserved += j->foot;
             ++running;
-            (j->small ? small_ready : large_ready).push_back(j);
+            if (j->tiny && teams_on) {
+                j->path = 0;
+                tiny_ready.push_back(j);
+            } else if (j->small) {
+                j->path = 1;
+                small_ready.push_back(j);
+            } else {
+                j->path = 2;
+                large_ready.push_back(j);
+            }
         }
         cv_work.notify_all();
     }
 
     void complete(EJob* j) {
         std::lock_guard<std::mutex> lk(mu);
+        ++served[j->path];
         if (j->counted) --heavy_running;
         reserved -= j->foot;
         --running;
@@ -268,6 +284,7 @@ struct wf_engine {
     void run_large(EJob* j, hipStream_t s);
     void worker();
     void batcher();
+    void teams();
 };
 
 // footprint estimate of a request (bytes of the arena it may occupy); the
@@ -289,6 +306,7 @@ static wf_status footprint(const wf_request* r, const double* src_xyz, const dou
         j->foot = model + inc_src + tables;
         j->small = L.npoints <= kSmallPoints;
         j->heavy = !j->small;
+        j->tiny = team_fits(L.nx, L.ny, L.nz);
     } else {
         // record scratch (predicted data, residual, partial sums), both
         // increment tables, adjoint pair and gradient, and a checkpoint pool:
@@ -593,6 +611,239 @@ void wf_engine::batcher() {
     set_thread_arena(nullptr);
 }
 
+// Resident teams (k_team): tiny forward shots are set up (model, point
+// tables, coefficients) on the thread's own stream and then launched in
+// groups of one (dimension, order); a launch's work-groups take its shots in
+// turn, each holding its shot's two fields in LDS to the end. Up to
+// kTeamLaunches launches run at once, each on its own stream, so shots that
+// arrive while others run start at once in the next free one. A launch
+// depends on nothing but its table: it never waits for other work.
+struct TeamLaunch {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;      // recorded after the launch
+    TeamJob* host = nullptr;      // pinned table
+    int cap = 0;
+    DevBuf dev;                   // the table, then the shot counter
+    std::vector<EJob*> jobs;      // in flight
+};
+
+namespace {
+
+constexpr int kTeamLaunches = 4;
+
+TeamJob team_job(const Model& md, const PointSet& src, const PointSet& rec, const wf_request& r,
+                 const float* inc) {
+    TeamJob J;
+    std::memset(&J, 0, sizeof J);
+    StepParams p;
+    md.fill_step(p, r.dt);
+    J.ndim = md.geom.ndim;
+    J.half = md.half;
+    J.nx = md.L.nx;
+    J.ny = md.L.ny;
+    J.nz = md.L.nz;
+    J.nt = r.nt;
+    J.nrec = rec.npts;
+    J.nnodes = src.nnodes;
+    J.c0 = p.c0;
+    J.inv2dt = p.inv2dt;
+    for (int j = 0; j <= kMaxHalf; ++j) {
+        J.wx[j] = p.wx[j];
+        J.wy[j] = p.wy[j];
+        J.wz[j] = p.wz[j];
+    }
+    J.sx = md.L.sx;
+    J.sy = md.L.sy;
+    J.kap = md.kap();
+    J.etax = p.etax;
+    J.etay = p.etay;
+    J.etaz = p.etaz;
+    J.noff = src.d_noff.as<int64_t>();
+    J.inc = inc;
+    J.smp_off = rec.d_off.as<int64_t>();
+    J.smp_w = rec.d_w.f();
+    J.rec = r.rec_out;
+    return J;
+}
+
+// the source increments of every step of a resident-team shot, by the
+// increment kernel of the other paths over the point set's node tables
+wf_status team_increments(const Model& md, const PointSet& src, const wf_request& r, DevBuf& buf,
+                          hipStream_t s) {
+    if (src.nnodes == 0 || r.nt < 2) return WF_OK;
+    const wf_status st = buf.alloc((int64_t)(r.nt - 1) * src.nnodes * 4);
+    if (st != WF_OK) return st;
+    StepParams p;
+    md.fill_step(p, r.dt);
+    IncParams ip{};
+    ip.inc = buf.f();
+    ip.kap = md.kap();
+    ip.off = src.d_noff.as<int64_t>();
+    ip.eta = src.d_neta.f();
+    ip.seg = src.d_seg.as<int>();
+    ip.pt = src.d_ept.as<int>();
+    ip.w = src.d_ew.f();
+    ip.vals = r.src_wav;
+    ip.nnodes = src.nnodes;
+    ip.npts = src.npts;
+    ip.nrows = r.nt - 1;
+    ip.inv2dt = p.inv2dt;
+    return hip_check(launch_increments(ip, s), "increments");
+}
+
+// table of `jobs` into `L` (growing it), then the launch and its event
+wf_status team_launch(TeamLaunch& L, const std::vector<EJob*>& jobs, int ndim, int half, int cus) {
+    const int n = (int)jobs.size();
+    if (n > L.cap) {
+        if (L.host) (void)hipHostFree(L.host);
+        L.host = nullptr;
+        L.cap = 0;
+        L.dev.reset();
+        const int cap = std::max(n, 256);
+        if (hipHostMalloc(reinterpret_cast<void**>(&L.host), sizeof(TeamJob) * cap) != hipSuccess) {
+            L.host = nullptr;
+            return fail(WF_E_NOMEM, "pinned team table");
+        }
+        const wf_status st = L.dev.alloc((int64_t)sizeof(TeamJob) * cap + 256);
+        if (st != WF_OK) return st;
+        L.cap = cap;
+    }
+    for (int i = 0; i < n; ++i) {
+        const EJob& j = *jobs[(size_t)i];
+        L.host[i] = team_job(*j.md, *j.ps_src, *j.ps_rec, j.rq, j.inc.f());
+    }
+    TeamArgs a;
+    a.jobs = L.dev.as<TeamJob>();
+    a.next = reinterpret_cast<unsigned int*>(L.dev.as<char>() + sizeof(TeamJob) * L.cap);
+    a.njobs = n;
+    wf_status st = hip_check(hipMemcpyAsync(L.dev.ptr, L.host, sizeof(TeamJob) * n, hipMemcpyHostToDevice, L.s),
+                             "team table");
+    if (st == WF_OK) st = hip_check(launch_fill(reinterpret_cast<float*>(a.next), 1, 0.0f, L.s), "team counter");
+    if (st == WF_OK) st = hip_check(launch_team(a, ndim, half, std::min(n, cus), L.s), "team launch");
+    if (st == WF_OK) st = hip_check(hipEventRecord(L.ev, L.s), "event");
+    return st;
+}
+
+}  // namespace
+
+void wf_engine::teams() {
+    (void)hipSetDevice(device);
+    hipStream_t s_setup = nullptr;
+    wf_status broken = hip_check(hipStreamCreateWithFlags(&s_setup, hipStreamNonBlocking), "stream");
+    set_thread_arena(arena, s_setup);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    TeamLaunch launches[kTeamLaunches];
+    for (TeamLaunch& L : launches) {
+        if (broken == WF_OK) broken = hip_check(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking), "stream");
+        if (broken == WF_OK) broken = hip_check(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming), "event");
+    }
+    auto finish = [&](EJob* j, wf_status st) {
+        if (j->st == WF_OK) j->st = st;
+        j->inc.reset();
+        delete j->md;
+        j->md = nullptr;
+        complete(j);
+    };
+    std::vector<EJob*> backlog;   // set up, waiting for a free launch
+    for (;;) {
+        bool busy = false;
+        for (TeamLaunch& L : launches) busy = busy || !L.jobs.empty();
+        std::vector<EJob*> fresh;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (!busy && backlog.empty()) cv_work.wait(lk, [&] { return stop || !tiny_ready.empty(); });
+            else if (tiny_ready.empty()) cv_work.wait_for(lk, std::chrono::microseconds(50));
+            while (!tiny_ready.empty()) {
+                fresh.push_back(tiny_ready.front());
+                tiny_ready.pop_front();
+            }
+            if (!busy && fresh.empty() && backlog.empty() && stop) break;
+        }
+        size_t k = 0;   // fresh[k..] not set up yet
+        try {
+            // set the arrivals up and wait until their inputs are in memory
+            const size_t nold = backlog.size();
+            for (; k < fresh.size(); ++k) {
+                EJob* j = fresh[k];
+                const wf_request& r = j->rq;
+                wf_status st = broken;
+                if (st == WF_OK) {
+                    j->md = new Model();
+                    st = j->wait_inputs(s_setup);
+                }
+                if (st == WF_OK) st = j->md->init(&r.geom, r.m_dev, s_setup);
+                if (st == WF_OK) st = j->md->check_dt(r.dt);
+                if (st == WF_OK) st = j->md->points(r.nsrc, j->src.data(), &j->ps_src);
+                if (st == WF_OK) st = j->md->points(r.nrec, j->rec.data(), &j->ps_rec);
+                if (st == WF_OK) st = j->md->ensure_kap(r.dt, s_setup);
+                if (st == WF_OK) st = team_increments(*j->md, *j->ps_src, r, j->inc, s_setup);
+                if (st == WF_OK) backlog.push_back(j);
+                else finish(j, st);
+            }
+            if (backlog.size() > nold) {
+                const wf_status st = hip_check(hipStreamSynchronize(s_setup), "set-up");
+                if (st != WF_OK) {
+                    for (size_t i = nold; i < backlog.size(); ++i) finish(backlog[i], st);
+                    backlog.resize(nold);
+                }
+            }
+            // retire finished launches
+            for (TeamLaunch& L : launches) {
+                if (L.jobs.empty()) continue;
+                const hipError_t q = hipEventQuery(L.ev);
+                if (q == hipErrorNotReady) continue;
+                const wf_status st = q == hipSuccess ? WF_OK : hip_check(q, "team launch");
+                std::vector<EJob*> done_jobs;
+                done_jobs.swap(L.jobs);
+                for (EJob* j : done_jobs) finish(j, st);
+            }
+            // launch what waits, one (ndim, half) group per free launch
+            while (!backlog.empty()) {
+                TeamLaunch* L = nullptr;
+                for (TeamLaunch& c : launches)
+                    if (c.jobs.empty() && !L) L = &c;
+                if (!L) break;
+                const int ndim = backlog.front()->md->geom.ndim, half = backlog.front()->md->half;
+                std::vector<EJob*> group, rest;
+                for (EJob* j : backlog) (j->md->geom.ndim == ndim && j->md->half == half ? group : rest).push_back(j);
+                backlog.swap(rest);
+                const wf_status st = team_launch(*L, group, ndim, half, cus);
+                if (st != WF_OK) {
+                    (void)hipStreamSynchronize(L->s);
+                    for (EJob* j : group) finish(j, st);
+                } else {
+                    L->jobs.swap(group);
+                }
+            }
+        } catch (...) {
+            // a host allocation failed: settle the launches, fail the rest
+            for (TeamLaunch& L : launches) {
+                (void)hipStreamSynchronize(L.s);
+                std::vector<EJob*> done_jobs;
+                done_jobs.swap(L.jobs);
+                for (EJob* j : done_jobs) finish(j, WF_OK);
+            }
+            (void)hipStreamSynchronize(s_setup);
+            const wf_status st = fail(WF_E_NOMEM, "host allocation failed while serving");
+            std::vector<EJob*> rest;
+            rest.swap(backlog);
+            for (; k < fresh.size(); ++k)
+                if (std::find(rest.begin(), rest.end(), fresh[k]) == rest.end()) rest.push_back(fresh[k]);
+            for (EJob* j : rest) finish(j, st);
+        }
+    }
+    for (TeamLaunch& L : launches) {
+        if (L.s) (void)hipStreamSynchronize(L.s);
+        if (L.host) (void)hipHostFree(L.host);
+        L.dev.reset();
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        if (L.s) (void)hipStreamDestroy(L.s);
+    }
+    if (s_setup) (void)hipStreamDestroy(s_setup);
+    set_thread_arena(nullptr);
+}
+
 extern "C" {
 
 wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** out) {
@@ -613,8 +864,10 @@ wf_status wf_engine_create(int64_t hbm_budget_bytes, int max_slots, wf_engine** 
         (void)hipGetDevice(&e->device);
         e->budget = hbm_budget_bytes;
         e->max_slots = max_slots;
+        if (const char* t = std::getenv("WAVEFD_TEAMS")) e->teams_on = t[0] != '0';
         for (int i = 0; i < kWorkers; ++i) e->threads.emplace_back([e] { e->worker(); });
         e->threads.emplace_back([e] { e->batcher(); });
+        e->threads.emplace_back([e] { e->teams(); });
         *out = e;
         return WF_OK;
     } catch (...) {
@@ -717,6 +970,16 @@ wf_status wf_engine_stats(const wf_engine* ce, int64_t* queued, int64_t* running
     if (running) *running = e->running;
     if (completed) *completed = e->completed;
     if (bytes_in_use) *bytes_in_use = arena_used(e->arena);
+    return WF_OK;
+}
+
+wf_status wf_engine_paths(const wf_engine* ce, int64_t* teams, int64_t* batched, int64_t* workers) {
+    if (!ce) return fail(WF_E_ARG, "engine is NULL");
+    wf_engine* e = const_cast<wf_engine*>(ce);
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (teams) *teams = e->served[0];
+    if (batched) *batched = e->served[1];
+    if (workers) *workers = e->served[2];
     return WF_OK;
 }
 

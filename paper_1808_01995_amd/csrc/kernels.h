@@ -102,6 +102,39 @@ struct BatchJob {
 hipError_t launch_step_batch(const BatchJob* jobs_dev, int njobs, int total_blocks, int ndim,
                              int half, int tile, int k, hipStream_t s);
 
+// Forward shots of grids small enough that both wavefields fit one
+// work-group's LDS (the serving engine's resident teams): each work-group of
+// a launch takes a shot from the launch's table, steps it to the end with
+// only work-group barriers (the fields never leave LDS), writes its record and
+// takes the next. The source increments are made beforehand by
+// launch_increments over the point set's node tables. Results equal
+// wf_forward's bit for bit (the same arithmetic in the same order).
+constexpr int kTeamThreads = 1024;
+constexpr int kTeamFieldFloats = 40640;   // two fields of nx * ny * round4(nz) floats
+struct TeamJob {
+    int ndim, half, nx, ny, nz, nt, nrec, nnodes;
+    float c0, inv2dt;
+    float wx[kMaxHalf + 1], wy[kMaxHalf + 1], wz[kMaxHalf + 1];
+    int64_t sx, sy;             // the model's pitched layout (offsets of kap and of the point tables)
+    const float* kap;
+    const float* etax;
+    const float* etay;
+    const float* etaz;
+    const int64_t* noff;        // source nodes (pitched offsets)
+    const float* inc;           // [nt-1][nnodes] their increments per step (k_increments)
+    const int64_t* smp_off;     // receiver corners (pitched offsets) and weights [nrec][2^ndim]
+    const float* smp_w;
+    float* rec;                 // [nt][nrec]
+};
+struct TeamArgs {
+    const TeamJob* jobs;        // device memory, njobs shots of one (ndim, half)
+    unsigned int* next;         // device memory, 0 at the launch
+    int njobs;
+};
+// A grid fits a team when both fields (z padded to 4) fit kTeamFieldFloats.
+bool team_fits(int64_t nx, int64_t ny, int64_t nz);
+hipError_t launch_team(const TeamArgs& a, int ndim, int half, int nwg, hipStream_t s);
+
 // Tile shapes (threads along z carry 4 points each).
 struct TileShape {
     int bz, by;   // threads along z and y per block

@@ -482,6 +482,241 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 }
 
 // ---------------------------------------------------------------------------
+// resident teams: one work-group steps one small grid held in LDS
+// ---------------------------------------------------------------------------
+// Dense LDS layout [x][y][zp], zp = z padded to 4 (the pad holds zeros).
+// Every quantity is formed as in step_body, in the same order, so each node
+// gets the same bits: lap = c0 c, then the x, y and z pairs (minus side
+// first) by fmaf, then update(); the sources' increments (made by
+// k_increments before the launch) are added after the update, the receivers
+// interpolated from the field before it, in k_sample's corner order.
+// Threads of a team: as many as keep every register of a thread's node
+// column (the x ring, the z window, the plane ahead) without spilling:
+// 1024 (16 waves, 128 VGPRs) for the 2D order-4 stencil, 256 for the 3D
+// order-16 one, 512 otherwise.
+__host__ __device__ constexpr int team_threads(bool d3, int m) {
+    return d3 ? (m >= 8 ? 256 : 512) : (m <= 2 ? kTeamThreads : 512);
+}
+
+template <bool D3, int M>
+__device__ void team_run(const TeamJob& J, float* F) {
+    constexpr int T = team_threads(D3, M);
+    constexpr int P = (M + 3) & ~3;
+    constexpr int HZ = P / 4;
+    constexpr int KS = D3 ? 8 : 4;   // corners of a receiver's cell
+    const int tid = threadIdx.x;
+    const int nx = J.nx, ny = J.ny, nz = J.nz;
+    // the job's scalars, read once (uniform: scalar registers)
+    const float c0 = J.c0, inv2dt = J.inv2dt;
+    float wx[M + 1], wy[M + 1], wz[M + 1];
+#pragma unroll
+    for (int j = 1; j <= M; ++j) {
+        wx[j] = J.wx[j];
+        wy[j] = J.wy[j];
+        wz[j] = J.wz[j];
+    }
+    const float* __restrict__ kap = J.kap;
+    const float* __restrict__ etax = J.etax;
+    const float* __restrict__ etay = J.etay;
+    const float* __restrict__ etaz = J.etaz;
+    const int64_t sxk = J.sx, syk = J.sy;
+    const int nzv = (nz + 3) / 4;
+    const int npts = nx * ny * nzv * 4;
+    float* A = F;          // u^n
+    float* B = F + npts;   // u^{n-1}, overwritten by u^{n+1}
+    for (int i = tid; i < 2 * npts; i += T) F[i] = 0.0f;
+    const int ncol = ny * nzv;
+    const int nch = max(1, T / ncol);
+    const int cx = (nx + nch - 1) / nch;
+    // pitched offset -> dense LDS index, by float reciprocals (a grid that
+    // fits has fewer than 2^24 pitched elements, so the quotient estimate is
+    // off by at most one, which the remainder test corrects)
+    const int sxi = (int)J.sx, syi = (int)J.sy;
+    const float rsx = 1.0f / (float)sxi, rsy = 1.0f / (float)syi;
+    auto dense = [&](int64_t o64) -> int {
+        const int o = (int)o64;
+        int x = (int)((float)o * rsx);
+        int r = o - x * sxi;
+        if (r < 0) {
+            --x;
+            r += sxi;
+        } else if (r >= sxi) {
+            ++x;
+            r -= sxi;
+        }
+        int y = (int)((float)r * rsy);
+        int z = r - y * syi;
+        if (z < 0) {
+            --y;
+            z += syi;
+        } else if (z >= syi) {
+            ++y;
+            z -= syi;
+        }
+        return (x * ny + y) * (nzv * 4) + z;
+    };
+    // the job's constant tables, converted once: the first receiver of each
+    // thread (2D; 3D receivers are many and their registers are needed by
+    // the stencil) and the first source node
+    int rd[KS];
+    float rw[KS];
+    const bool rcache = !D3 && tid < J.nrec;
+    if (rcache) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            rd[k] = dense(J.smp_off[(int64_t)tid * KS + k]);
+            rw[k] = J.smp_w[(int64_t)tid * KS + k];
+        }
+    }
+    const int nd = tid < J.nnodes ? dense(J.noff[tid]) : 0;
+    __syncthreads();
+    auto sample = [&](const float* U, int row) {
+        int i = tid;
+        if (rcache) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) acc = fmaf(rw[k], U[rd[k]], acc);
+            J.rec[(int64_t)row * J.nrec + i] = acc;
+            i += T;
+        }
+        for (; i < J.nrec; i += T) {
+            int so[KS];
+            float sw[KS];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                so[k] = (int)J.smp_off[(int64_t)i * KS + k];
+                sw[k] = J.smp_w[(int64_t)i * KS + k];
+            }
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) acc = fmaf(sw[k], U[dense(so[k])], acc);
+            J.rec[(int64_t)row * J.nrec + i] = acc;
+        }
+    };
+    auto vec = [&](const float* U, int x, int y, int zv) -> float4 {
+        if (x < 0 || x >= nx || y < 0 || y >= ny || zv < 0 || zv >= nzv) return zero4();
+        return reinterpret_cast<const float4*>(U)[(x * ny + y) * nzv + zv];
+    };
+    for (int n = 0; n + 1 < J.nt; ++n) {
+        // this step's increment of the thread's source node, used after the
+        // update (its latency hides behind it)
+        const float incv = tid < J.nnodes ? J.inc[(int64_t)n * J.nnodes + tid] : 0.0f;
+        sample(A, n);
+        for (int item = tid; item < ncol * nch; item += T) {
+            const int col = item % ncol, ch = item / ncol;
+            const int y = col / nzv, zv = col - y * nzv, z = 4 * zv;
+            const int x0 = ch * cx, x1 = min(nx, x0 + cx);
+            if (x0 >= x1) continue;
+            float4 r[2 * M + 1];
+#pragma unroll
+            for (int i = 0; i < 2 * M + 1; ++i) r[i] = vec(A, x0 - M + i, y, zv);
+            float eyz[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) eyz[i] = z + i < nz ? ((D3 ? etay[y] : 0.0f) + etaz[z + i]) : 0.0f;
+            // kappa and eta_x of the next plane are loaded one plane ahead
+            const float* kcol = kap + (int64_t)y * syk + z;
+            float4 kp_n = ld4(kcol + (int64_t)x0 * sxk);
+            float ex_n = etax[x0];
+            for (int x = x0; x < x1; ++x) {
+                const float4 kp = kp_n;
+                const float ex = ex_n;
+                if (x + 1 < x1) {
+                    kp_n = ld4(kcol + (int64_t)(x + 1) * sxk);
+                    ex_n = etax[x + 1];
+                }
+                const float4 c = r[M];
+                float lap[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) lap[i] = c0 * comp(c, i);
+#pragma unroll
+                for (int j = 1; j <= M; ++j) {
+                    const float4 a = r[M - j], b = r[M + j];
+                    lap[0] = fmaf(wx[j], a.x + b.x, lap[0]);
+                    lap[1] = fmaf(wx[j], a.y + b.y, lap[1]);
+                    lap[2] = fmaf(wx[j], a.z + b.z, lap[2]);
+                    lap[3] = fmaf(wx[j], a.w + b.w, lap[3]);
+                }
+                if (D3) {
+#pragma unroll
+                    for (int j = 1; j <= M; ++j) {
+                        const float4 a = vec(A, x, y - j, zv), b = vec(A, x, y + j, zv);
+                        lap[0] = fmaf(wy[j], a.x + b.x, lap[0]);
+                        lap[1] = fmaf(wy[j], a.y + b.y, lap[1]);
+                        lap[2] = fmaf(wy[j], a.z + b.z, lap[2]);
+                        lap[3] = fmaf(wy[j], a.w + b.w, lap[3]);
+                    }
+                }
+                {
+                    float w[2 * P + 4];
+#pragma unroll
+                    for (int k = 0; k < 2 * HZ + 1; ++k) {
+                        const float4 v = k == HZ ? c : vec(A, x, y, zv - HZ + k);
+                        w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 1; j <= M; ++j)
+                            lap[i] = fmaf(wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+                }
+                const float4 uo = vec(B, x, y, zv);
+                float4 o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], inv2dt);
+                    if (z + i >= nz) v = 0.0f;
+                    set_comp(o, i, v);
+                }
+                reinterpret_cast<float4*>(B)[(x * ny + y) * nzv + zv] = o;
+#pragma unroll
+                for (int i = 0; i < 2 * M; ++i) r[i] = r[i + 1];
+                r[2 * M] = vec(A, x + M + 1, y, zv);
+            }
+        }
+        __syncthreads();
+        // q^n into u^{n+1}: one thread per source node
+        if (tid < J.nnodes) B[nd] += incv;
+        for (int k = tid + T; k < J.nnodes; k += T) B[dense(J.noff[k])] += J.inc[(int64_t)n * J.nnodes + k];
+        __syncthreads();
+        float* t = A;
+        A = B;
+        B = t;
+    }
+    if (J.nt > 1) {
+        sample(A, J.nt - 1);
+    } else {
+        for (int i = tid; i < J.nrec; i += T) J.rec[i] = 0.0f;
+    }
+}
+
+__device__ inline bool team_fits_dev(int nx, int ny, int nz) {
+    return nx > 0 && ny > 0 && nz > 0 && (int64_t)nx * ny * ((nz + 3) / 4 * 4) * 2 <= kTeamFieldFloats;
+}
+
+// A launch of resident teams: work-groups take the launch's shots in order
+// (one counter in device memory, zero at the launch), each stepping its shot
+// to the end in LDS before it takes the next. The job is read from the table
+// with a uniform index, so its scalars live in scalar registers.
+template <bool D3, int M>
+__global__ void __launch_bounds__(team_threads(D3, M), 1) k_team(const TeamArgs a) {
+    __shared__ __attribute__((aligned(16))) float F[kTeamFieldFloats];
+    __shared__ int s_j;
+    const TeamJob* __restrict__ jobs = a.jobs;
+    for (;;) {
+        if (threadIdx.x == 0) s_j = (int)atomicAdd(a.next, 1u);
+        __syncthreads();
+        const int j = __builtin_amdgcn_readfirstlane(s_j);
+        __syncthreads();   // s_j is rewritten for the next shot
+        if (j >= a.njobs) return;   // uniform
+        const TeamJob& J = jobs[j];
+        // the host groups shots by (ndim, half) and admits only grids that
+        // fit; a table entry that does not is skipped rather than overrun LDS
+        if (J.ndim == (D3 ? 3 : 2) && J.half == M && team_fits_dev(J.nx, J.ny, J.nz)) team_run<D3, M>(J, F);
+        __syncthreads();   // F is cleared for the next shot
+    }
+}
+
+// ---------------------------------------------------------------------------
 // sparse operators and helpers
 // ---------------------------------------------------------------------------
 __global__ void k_inject(const InjectParams p) {
@@ -846,6 +1081,31 @@ hipError_t launch_step_batch(const BatchJob* jobs, int njobs, int total, int ndi
         case 8: return launch_batch_m<8>(jobs, njobs, total, ndim, tile, k, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+bool team_fits(int64_t nx, int64_t ny, int64_t nz) {
+    return nx > 0 && ny > 0 && nz > 0 && nx * ny * ((nz + 3) / 4 * 4) * 2 <= kTeamFieldFloats;
+}
+
+template <bool D3>
+hipError_t launch_team_d(const TeamArgs& a, int half, int nwg, hipStream_t s) {
+    const dim3 g(nwg);
+    switch (half) {
+        case 2: hipLaunchKernelGGL((k_team<D3, 2>), g, dim3(team_threads(D3, 2)), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_team<D3, 3>), g, dim3(team_threads(D3, 3)), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_team<D3, 4>), g, dim3(team_threads(D3, 4)), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_team<D3, 5>), g, dim3(team_threads(D3, 5)), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_team<D3, 6>), g, dim3(team_threads(D3, 6)), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_team<D3, 7>), g, dim3(team_threads(D3, 7)), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_team<D3, 8>), g, dim3(team_threads(D3, 8)), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_team(const TeamArgs& a, int ndim, int half, int nwg, hipStream_t s) {
+    if (nwg <= 0) return hipSuccess;
+    return ndim == 3 ? launch_team_d<true>(a, half, nwg, s) : launch_team_d<false>(a, half, nwg, s);
 }
 
 hipError_t launch_inject(const InjectParams& p, hipStream_t s) {

@@ -204,6 +204,32 @@ wf_status DevBuf::upload(const void* host, int64_t nbytes) {
     return WF_OK;
 }
 
+wf_status upload_packed(DevBuf& pack, std::initializer_list<UploadPart> parts) {
+    int64_t total = 0;
+    for (const UploadPart& q : parts) total = (total + 255) / 256 * 256 + std::max<int64_t>(q.bytes, 0);
+    std::vector<char> host((size_t)total);
+    int64_t off = 0;
+    for (const UploadPart& q : parts) {
+        off = (off + 255) / 256 * 256;
+        if (q.bytes > 0) std::memcpy(host.data() + off, q.host, (size_t)q.bytes);
+        off += std::max<int64_t>(q.bytes, 0);
+    }
+    for (const UploadPart& q : parts) q.buf->reset();
+    wf_status st = pack.upload(host.data(), total);
+    if (st != WF_OK) return st;
+    off = 0;
+    for (const UploadPart& q : parts) {
+        off = (off + 255) / 256 * 256;
+        if (q.bytes > 0) {
+            q.buf->ptr = static_cast<char*>(pack.ptr) + off;
+            q.buf->bytes = q.bytes;
+            q.buf->external = true;
+        }
+        off += std::max<int64_t>(q.bytes, 0);
+    }
+    return WF_OK;
+}
+
 wf_status hip_check(hipError_t e, const char* what) {
     if (e == hipSuccess) return WF_OK;
     (void)hipGetLastError();
@@ -307,10 +333,7 @@ wf_status PointSet::build(const wf_geom* g, const Layout& L, int npts_, const do
     std::vector<float> w, e;
     wf_status st = build_points(g, L, npts, xyz, off, w, &e);
     if (st != WF_OK) return st;
-    // sampling table: as is
-    if ((st = d_off.upload(off.data(), (int64_t)off.size() * 8)) != WF_OK) return st;
-    if ((st = d_w.upload(w.data(), (int64_t)w.size() * 4)) != WF_OK) return st;
-    // injection table: entries grouped by node, in (point, corner) order inside
+    // sampling table: as is; injection table: entries grouped by node, in (point, corner) order inside
     // a node, so every node is summed by one thread in a fixed order
     const size_t ne = off.size();
     std::vector<size_t> idx(ne);
@@ -331,11 +354,14 @@ wf_status PointSet::build(const wf_geom* g, const Layout& L, int npts_, const do
     }
     seg.push_back((int)ne);
     nnodes = (int)noff.size();
-    if ((st = d_noff.upload(noff.data(), (int64_t)noff.size() * 8)) != WF_OK) return st;
-    if ((st = d_neta.upload(neta.data(), (int64_t)neta.size() * 4)) != WF_OK) return st;
-    if ((st = d_seg.upload(seg.data(), (int64_t)seg.size() * 4)) != WF_OK) return st;
-    if ((st = d_ept.upload(ept.data(), (int64_t)ept.size() * 4)) != WF_OK) return st;
-    if ((st = d_ew.upload(ew.data(), (int64_t)ew.size() * 4)) != WF_OK) return st;
+    st = upload_packed(d_pack, {{&d_off, off.data(), (int64_t)off.size() * 8},
+                                {&d_w, w.data(), (int64_t)w.size() * 4},
+                                {&d_noff, noff.data(), (int64_t)noff.size() * 8},
+                                {&d_neta, neta.data(), (int64_t)neta.size() * 4},
+                                {&d_seg, seg.data(), (int64_t)seg.size() * 4},
+                                {&d_ept, ept.data(), (int64_t)ept.size() * 4},
+                                {&d_ew, ew.data(), (int64_t)ew.size() * 4}});
+    if (st != WF_OK) return st;
     h_noff = std::move(noff);
     h_neta = std::move(neta);
     h_seg = std::move(seg);
@@ -481,9 +507,10 @@ wf_status Model::init(const wf_geom* g, const float* m_dev, hipStream_t s) {
     std::vector<float> ex = eta_profile(g, 0);
     std::vector<float> ey = g->ndim == 3 ? eta_profile(g, 1) : std::vector<float>(1, 0.0f);
     std::vector<float> ez = eta_profile(g, g->ndim - 1);
-    if ((st = d_etax.upload(ex.data(), (int64_t)ex.size() * 4)) != WF_OK) return st;
-    if ((st = d_etay.upload(ey.data(), (int64_t)ey.size() * 4)) != WF_OK) return st;
-    if ((st = d_etaz.upload(ez.data(), (int64_t)ez.size() * 4)) != WF_OK) return st;
+    st = upload_packed(d_eta_pack, {{&d_etax, ex.data(), (int64_t)ex.size() * 4},
+                                    {&d_etay, ey.data(), (int64_t)ey.size() * 4},
+                                    {&d_etaz, ez.data(), (int64_t)ez.size() * 4}});
+    if (st != WF_OK) return st;
     if ((st = d_scratch.alloc(256)) != WF_OK) return st;
     return set_m(m_dev, s);
 }

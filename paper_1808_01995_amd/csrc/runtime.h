@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <initializer_list>
 #include <vector>
 
 #include "../../include/wavefd.h"
@@ -69,6 +70,16 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
 
+// Several small host tables uploaded with one synchronous copy: `pack`
+// receives them at 256-byte aligned offsets and each part's DevBuf becomes a
+// view into it (nothing of its own to free; valid while `pack` is).
+struct UploadPart {
+    DevBuf* buf;
+    const void* host;
+    int64_t bytes;
+};
+wf_status upload_packed(DevBuf& pack, std::initializer_list<UploadPart> parts);
+
 // Pitched field layout of a computational grid: element (x, y, z) at
 // x*sx + y*sy + z with sy >= nz a multiple of 4 (pad entries stay zero).
 struct Layout {
@@ -103,6 +114,7 @@ struct FusedInj {
 struct PointSet {
     int npts = 0, K = 0, nnodes = 0;
     int64_t gen = 0;                            // unique id of this table (graph keys)
+    DevBuf d_pack;                              // holds the tables below
     DevBuf d_off, d_w;                          // [npts*K]
     DevBuf d_noff, d_neta, d_seg, d_ept, d_ew;  // injection by node
     std::vector<int64_t> h_noff;                // host copies of the node tables
@@ -142,7 +154,7 @@ struct Model : public wf_model {
     int half = 0;
     wf::Layout L;
     double alpha[wf::kMaxHalf + 1]{};
-    wf::DevBuf d_m, d_kap, d_u[2], d_etax, d_etay, d_etaz, d_scratch;
+    wf::DevBuf d_m, d_kap, d_u[2], d_eta_pack, d_etax, d_etay, d_etaz, d_scratch;
     wf::DevBuf d_inc[2];   // precomputed injection increments (grow-only, stream-ordered reuse)
     wf::DevBuf ws;         // gradient workspace (checkpoint pool + adjoint pair), kept between calls
     bool ws_clean = false; // every ghost plane in ws is zero
@@ -195,8 +207,7 @@ struct Model : public wf_model {
     float* u(int i) const { return L.field(d_u[i].ptr); }
     float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
-        return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_etax.bytes + d_etay.bytes +
-               d_etaz.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes + ws.bytes;
+        return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_eta_pack.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes + ws.bytes;
     }
 };
 

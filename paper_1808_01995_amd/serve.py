@@ -179,6 +179,10 @@ class Server:
     def stats(self):
         return _abi.wf_engine_stats(self.handle)
 
+    def paths(self):
+        """Completed requests by path: resident teams, batched launches, workers."""
+        return _abi.wf_engine_paths(self.handle)
+
     def drain(self):
         while self.inflight:
             self.poll(wait_ms=50)

@@ -298,3 +298,56 @@ def test_submission_is_stream_ordered_and_admits_during_a_heavy_request():
     assert t_sub < 0.02
     assert small.done < heavy.done
     assert torch.equal(small.rec_out, ref)
+
+
+def test_resident_teams_equal_batched_launches_plain_propagator_and_oracle():
+    """Forward shots whose two wavefields fit one work-group's LDS run as
+    resident teams (2D 141^2 order 4 twice; 2D 90^2 order 8; 2D 80^2 order
+    12; 3D 26^3 order 8; submitted at once, so in launches of each order):
+    every record equals the batched launches' (resident teams switched off)
+    and the plain propagator's bit for bit, and the oracle's to the record
+    bar."""
+    import os
+    import oracle
+    from _harness import check_record
+    from paper_1808_01995_amd.serve import Server, build_request, run_one_shot_baseline, run_stream
+    specs = [({"ndim": 2, "n": 101, "space_order": 4, "steps": 300, "kind": "forward", "seed": 110}, 20),
+             ({"ndim": 2, "n": 101, "space_order": 4, "steps": 240, "kind": "forward", "seed": 111}, 20),
+             ({"ndim": 2, "n": 70, "space_order": 8, "steps": 200, "kind": "forward", "seed": 112}, 10),
+             ({"ndim": 2, "n": 60, "space_order": 12, "steps": 180, "kind": "forward", "seed": 113}, 10),
+             ({"ndim": 3, "n": 10, "space_order": 8, "steps": 120, "kind": "forward", "seed": 114}, 8)]
+    reqs = [build_request(sp, nbl=nbl) for sp, nbl in specs]
+    srv = Server(hbm_budget_bytes=2 << 30, max_slots=16)
+    st = run_stream(srv, reqs)
+    paths = srv.paths()
+    srv.close()
+    assert st["failed"] == 0 and paths["teams"] == len(reqs), paths
+    teams = [r.rec_out.clone() for r in reqs]
+    os.environ["WAVEFD_TEAMS"] = "0"
+    try:
+        srv = Server(hbm_budget_bytes=2 << 30, max_slots=16)
+        for r in reqs:
+            r.rec_out.fill_(float("nan"))
+        st = run_stream(srv, reqs)
+        paths = srv.paths()
+        srv.close()
+    finally:
+        del os.environ["WAVEFD_TEAMS"]
+    assert st["failed"] == 0 and paths["batched"] == len(reqs), paths
+    base = run_one_shot_baseline(reqs)
+    for i, (r, (d, _)) in enumerate(zip(reqs, base["outputs"])):
+        assert torch.equal(teams[i], r.rec_out), i
+        assert torch.equal(teams[i], d), i
+    for i in (0, 4):
+        r = reqs[i]
+        g = r.geom
+        nd = g.ndim
+        h = tuple(g.h[a] for a in range(nd))
+        shape = tuple(g.n[a] + 2 * g.nbl for a in range(nd))
+        og = oracle.Grid(shape, h, g.space_order)
+        eta = oracle.damping_eta(tuple(g.n[a] for a in range(nd)), g.nbl, h, g.c_ref)
+        ps = oracle.sparse_points(r.src_xyz, h, g.nbl, shape)
+        pr = oracle.sparse_points(r.rec_xyz, h, g.nbl, shape)
+        d_ref = oracle.forward(og, r.m.cpu().numpy().astype(np.float64), eta, r.dt, r.nt, ps,
+                               r.src_wav.cpu().numpy().astype(np.float64), pr)
+        check_record(teams[i].cpu().numpy(), d_ref, label="resident team %dD order %d" % (nd, g.space_order))
