@@ -525,9 +525,10 @@ __device__ void team_run(const TeamJob& J, float* F) {
     float* A = F;          // u^n
     float* B = F + npts;   // u^{n-1}, overwritten by u^{n+1}
     for (int i = tid; i < 2 * npts; i += T) F[i] = 0.0f;
+    // work items: a (y, z/4) column times a chunk of x planes; the chunks
+    // split nx as evenly as possible (sizes differ by at most one plane)
     const int ncol = ny * nzv;
-    const int nch = max(1, T / ncol);
-    const int cx = (nx + nch - 1) / nch;
+    const int nch = max(1, min(T / ncol, nx));
     // pitched offset -> dense LDS index, by float reciprocals (a grid that
     // fits has fewer than 2^24 pitched elements, so the quotient estimate is
     // off by at most one, which the remainder test corrects)
@@ -593,84 +594,111 @@ __device__ void team_run(const TeamJob& J, float* F) {
             J.rec[(int64_t)row * J.nrec + i] = acc;
         }
     };
-    auto vec = [&](const float* U, int x, int y, int zv) -> float4 {
-        if (x < 0 || x >= nx || y < 0 || y >= ny || zv < 0 || zv >= nzv) return zero4();
-        return reinterpret_cast<const float4*>(U)[(x * ny + y) * nzv + zv];
-    };
+    const int psx = ny * nzv;   // float4 per x plane
     for (int n = 0; n + 1 < J.nt; ++n) {
         // this step's increment of the thread's source node, used after the
         // update (its latency hides behind it)
         const float incv = tid < J.nnodes ? J.inc[(int64_t)n * J.nnodes + tid] : 0.0f;
         sample(A, n);
+        const float4* __restrict__ A4 = reinterpret_cast<const float4*>(A);
+        float4* __restrict__ B4 = reinterpret_cast<float4*>(B);
         for (int item = tid; item < ncol * nch; item += T) {
             const int col = item % ncol, ch = item / ncol;
             const int y = col / nzv, zv = col - y * nzv, z = 4 * zv;
-            const int x0 = ch * cx, x1 = min(nx, x0 + cx);
+            const int x0 = ch * nx / nch, x1 = (ch + 1) * nx / nch;
             if (x0 >= x1) continue;
-            float4 r[2 * M + 1];
+            const int cb = y * nzv + zv;   // the column in a plane (float4)
+            // which z and y neighbour columns lie inside the grid (outside: zero)
+            bool zok[2 * HZ + 1];
 #pragma unroll
-            for (int i = 0; i < 2 * M + 1; ++i) r[i] = vec(A, x0 - M + i, y, zv);
+            for (int k = 0; k < 2 * HZ + 1; ++k) zok[k] = zv - HZ + k >= 0 && zv - HZ + k < nzv;
+            bool ylo[M + 1], yhi[M + 1];
+#pragma unroll
+            for (int j = 1; j <= M; ++j) {
+                ylo[j] = D3 && y - j >= 0;
+                yhi[j] = D3 && y + j < ny;
+            }
+            // x ring: planes x - M .. x + M of the column, and x + M + 1
+            // loaded a plane ahead; the walk is unrolled by the ring length,
+            // so every slot index is a constant
+            constexpr int NR = 2 * M + 2;
+            float4 r[NR];
+#pragma unroll
+            for (int i = 0; i < 2 * M + 1; ++i) {
+                const int xx = x0 - M + i;
+                r[i] = xx >= 0 && xx < nx ? A4[xx * psx + cb] : zero4();
+            }
             float eyz[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) eyz[i] = z + i < nz ? ((D3 ? etay[y] : 0.0f) + etaz[z + i]) : 0.0f;
-            // kappa and eta_x of the next plane are loaded one plane ahead
+            // kappa and eta_x of plane x + 1 are loaded while plane x is
+            // computed (two slots; NR is even, so the slot is constant)
             const float* kcol = kap + (int64_t)y * syk + z;
-            float4 kp_n = ld4(kcol + (int64_t)x0 * sxk);
-            float ex_n = etax[x0];
-            for (int x = x0; x < x1; ++x) {
-                const float4 kp = kp_n;
-                const float ex = ex_n;
-                if (x + 1 < x1) {
-                    kp_n = ld4(kcol + (int64_t)(x + 1) * sxk);
-                    ex_n = etax[x + 1];
-                }
-                const float4 c = r[M];
-                float lap[4];
+            float4 kq[2];
+            float eq[2];
+            kq[0] = ld4(kcol + (int64_t)x0 * sxk);
+            eq[0] = etax[x0];
+            for (int xg = x0; xg < x1; xg += NR) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) lap[i] = c0 * comp(c, i);
+                for (int ph = 0; ph < NR; ++ph) {
+                    const int x = xg + ph;
+                    if (x < x1) {
+                        const int xn = x + M + 1;
+                        r[(ph + 2 * M + 1) % NR] = xn < nx ? A4[xn * psx + cb] : zero4();
+                        if (x + 1 < x1) {
+                            kq[(ph + 1) % 2] = ld4(kcol + (int64_t)(x + 1) * sxk);
+                            eq[(ph + 1) % 2] = etax[x + 1];
+                        }
+                        const float4 kp = kq[ph % 2];
+                        const float ex = eq[ph % 2];
+                        const int pc = x * psx + cb;
+                        const float4 c = r[(ph + M) % NR];
+                        float lap[4];
 #pragma unroll
-                for (int j = 1; j <= M; ++j) {
-                    const float4 a = r[M - j], b = r[M + j];
-                    lap[0] = fmaf(wx[j], a.x + b.x, lap[0]);
-                    lap[1] = fmaf(wx[j], a.y + b.y, lap[1]);
-                    lap[2] = fmaf(wx[j], a.z + b.z, lap[2]);
-                    lap[3] = fmaf(wx[j], a.w + b.w, lap[3]);
-                }
-                if (D3) {
+                        for (int i = 0; i < 4; ++i) lap[i] = c0 * comp(c, i);
 #pragma unroll
-                    for (int j = 1; j <= M; ++j) {
-                        const float4 a = vec(A, x, y - j, zv), b = vec(A, x, y + j, zv);
-                        lap[0] = fmaf(wy[j], a.x + b.x, lap[0]);
-                        lap[1] = fmaf(wy[j], a.y + b.y, lap[1]);
-                        lap[2] = fmaf(wy[j], a.z + b.z, lap[2]);
-                        lap[3] = fmaf(wy[j], a.w + b.w, lap[3]);
+                        for (int j = 1; j <= M; ++j) {
+                            const float4 a = r[(ph + M - j) % NR], b = r[(ph + M + j) % NR];
+                            lap[0] = fmaf(wx[j], a.x + b.x, lap[0]);
+                            lap[1] = fmaf(wx[j], a.y + b.y, lap[1]);
+                            lap[2] = fmaf(wx[j], a.z + b.z, lap[2]);
+                            lap[3] = fmaf(wx[j], a.w + b.w, lap[3]);
+                        }
+                        if (D3) {
+#pragma unroll
+                            for (int j = 1; j <= M; ++j) {
+                                const float4 a = ylo[j] ? A4[pc - j * nzv] : zero4();
+                                const float4 b = yhi[j] ? A4[pc + j * nzv] : zero4();
+                                lap[0] = fmaf(wy[j], a.x + b.x, lap[0]);
+                                lap[1] = fmaf(wy[j], a.y + b.y, lap[1]);
+                                lap[2] = fmaf(wy[j], a.z + b.z, lap[2]);
+                                lap[3] = fmaf(wy[j], a.w + b.w, lap[3]);
+                            }
+                        }
+                        {
+                            float w[2 * P + 4];
+#pragma unroll
+                            for (int k = 0; k < 2 * HZ + 1; ++k) {
+                                const float4 v = k == HZ ? c : (zok[k] ? A4[pc - HZ + k] : zero4());
+                                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                            }
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                                for (int j = 1; j <= M; ++j)
+                                    lap[i] = fmaf(wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+                        }
+                        const float4 uo = B4[pc];
+                        float4 o;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], inv2dt);
+                            if (z + i >= nz) v = 0.0f;
+                            set_comp(o, i, v);
+                        }
+                        B4[pc] = o;
                     }
                 }
-                {
-                    float w[2 * P + 4];
-#pragma unroll
-                    for (int k = 0; k < 2 * HZ + 1; ++k) {
-                        const float4 v = k == HZ ? c : vec(A, x, y, zv - HZ + k);
-                        w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 1; j <= M; ++j)
-                            lap[i] = fmaf(wz[j], w[P + i - j] + w[P + i + j], lap[i]);
-                }
-                const float4 uo = vec(B, x, y, zv);
-                float4 o;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], inv2dt);
-                    if (z + i >= nz) v = 0.0f;
-                    set_comp(o, i, v);
-                }
-                reinterpret_cast<float4*>(B)[(x * ny + y) * nzv + zv] = o;
-#pragma unroll
-                for (int i = 0; i < 2 * M; ++i) r[i] = r[i + 1];
-                r[2 * M] = vec(A, x + M + 1, y, zv);
             }
         }
         __syncthreads();
