@@ -630,6 +630,7 @@ struct TeamLaunch {
 namespace {
 
 constexpr int kTeamLaunches = 4;
+constexpr int64_t kTeamStagingBytes = (int64_t)8 << 20;   // pinned staging of the set-up uploads of a batch
 
 TeamJob team_job(const Model& md, const PointSet& src, const PointSet& rec, const wf_request& r,
                  const float* inc) {
@@ -745,7 +746,19 @@ void wf_engine::teams() {
         j->md = nullptr;
         complete(j);
     };
+    // set-up of a batch of arrivals is queued without a host wait: small
+    // uploads go through pinned staging, the check of each m lands in a
+    // pinned slot, and one synchronisation covers the batch
+    PinnedStaging staging;
+    staging.stream = s_setup;
+    if (hipHostMalloc(reinterpret_cast<void**>(&staging.base), kTeamStagingBytes) == hipSuccess)
+        staging.size = kTeamStagingBytes;
+    else
+        staging.base = nullptr;
+    unsigned int* host3 = nullptr;   // pinned, 4 per arrival of a batch
+    size_t host3_cap = 0;
     std::vector<EJob*> backlog;   // set up, waiting for a free launch
+    std::vector<EJob*> pend;      // set up, the check of m pending
     for (;;) {
         bool busy = false;
         for (TeamLaunch& L : launches) busy = busy || !L.jobs.empty();
@@ -762,31 +775,49 @@ void wf_engine::teams() {
         }
         size_t k = 0;   // fresh[k..] not set up yet
         try {
-            // set the arrivals up and wait until their inputs are in memory
-            const size_t nold = backlog.size();
+            // set the arrivals up (waiting for their inputs on the set-up
+            // stream), then wait once for all of them and check each m and dt
+            if (fresh.size() > host3_cap) {
+                if (host3) (void)hipHostFree(host3);
+                host3 = nullptr;
+                host3_cap = 0;
+                const size_t cap = std::max<size_t>(fresh.size(), 256);
+                if (hipHostMalloc(reinterpret_cast<void**>(&host3), cap * 4 * sizeof(unsigned int)) != hipSuccess)
+                    host3 = nullptr;
+                else
+                    host3_cap = cap;
+            }
+            if (staging.used > 0) (void)hipStreamSynchronize(s_setup);   // its copies have passed
+            staging.used = 0;
+            set_thread_staging(staging.base ? &staging : nullptr);
             for (; k < fresh.size(); ++k) {
                 EJob* j = fresh[k];
                 const wf_request& r = j->rq;
-                wf_status st = broken;
+                wf_status st = host3 ? broken : fail(WF_E_NOMEM, "pinned host slots");
                 if (st == WF_OK) {
                     j->md = new Model();
                     st = j->wait_inputs(s_setup);
                 }
-                if (st == WF_OK) st = j->md->init(&r.geom, r.m_dev, s_setup);
-                if (st == WF_OK) st = j->md->check_dt(r.dt);
+                if (st == WF_OK) st = j->md->init_pending(&r.geom, r.m_dev, s_setup, host3 + 4 * pend.size());
                 if (st == WF_OK) st = j->md->points(r.nsrc, j->src.data(), &j->ps_src);
                 if (st == WF_OK) st = j->md->points(r.nrec, j->rec.data(), &j->ps_rec);
                 if (st == WF_OK) st = j->md->ensure_kap(r.dt, s_setup);
                 if (st == WF_OK) st = team_increments(*j->md, *j->ps_src, r, j->inc, s_setup);
-                if (st == WF_OK) backlog.push_back(j);
+                if (st == WF_OK) pend.push_back(j);
                 else finish(j, st);
             }
-            if (backlog.size() > nold) {
+            set_thread_staging(nullptr);
+            if (!pend.empty()) {
                 const wf_status st = hip_check(hipStreamSynchronize(s_setup), "set-up");
-                if (st != WF_OK) {
-                    for (size_t i = nold; i < backlog.size(); ++i) finish(backlog[i], st);
-                    backlog.resize(nold);
+                for (size_t i = 0; i < pend.size(); ++i) {
+                    EJob* j = pend[i];
+                    wf_status sj = st;
+                    if (sj == WF_OK) sj = j->md->finish_m(host3 + 4 * i);
+                    if (sj == WF_OK) sj = j->md->check_dt(j->rq.dt);
+                    if (sj == WF_OK) backlog.push_back(j);
+                    else finish(j, sj);
                 }
+                pend.clear();
             }
             // retire finished launches
             for (TeamLaunch& L : launches) {
@@ -818,6 +849,7 @@ void wf_engine::teams() {
             }
         } catch (...) {
             // a host allocation failed: settle the launches, fail the rest
+            set_thread_staging(nullptr);
             for (TeamLaunch& L : launches) {
                 (void)hipStreamSynchronize(L.s);
                 std::vector<EJob*> done_jobs;
@@ -828,6 +860,8 @@ void wf_engine::teams() {
             const wf_status st = fail(WF_E_NOMEM, "host allocation failed while serving");
             std::vector<EJob*> rest;
             rest.swap(backlog);
+            rest.insert(rest.end(), pend.begin(), pend.end());
+            pend.clear();
             for (; k < fresh.size(); ++k)
                 if (std::find(rest.begin(), rest.end(), fresh[k]) == rest.end()) rest.push_back(fresh[k]);
             for (EJob* j : rest) finish(j, st);
@@ -840,6 +874,9 @@ void wf_engine::teams() {
         if (L.ev) (void)hipEventDestroy(L.ev);
         if (L.s) (void)hipStreamDestroy(L.s);
     }
+    if (s_setup) (void)hipStreamSynchronize(s_setup);
+    if (staging.base) (void)hipHostFree(staging.base);
+    if (host3) (void)hipHostFree(host3);
     if (s_setup) (void)hipStreamDestroy(s_setup);
     set_thread_arena(nullptr);
 }

@@ -126,7 +126,9 @@ std::vector<float> eta_profile(const wf_geom* g, int axis) {
 static thread_local Arena* t_arena = nullptr;
 static thread_local hipStream_t t_arena_stream = nullptr;
 static thread_local ScratchRegion* t_scratch = nullptr;
+static thread_local PinnedStaging* t_staging = nullptr;
 void set_thread_scratch(ScratchRegion* r) { t_scratch = r; }
+void set_thread_staging(PinnedStaging* p) { t_staging = p; }
 bool thread_scratch_active() { return t_scratch != nullptr; }
 void set_thread_arena(Arena* a, hipStream_t s) {
     t_arena = a;
@@ -199,6 +201,16 @@ wf_status DevBuf::upload(const void* host, int64_t nbytes) {
     wf_status st = alloc(nbytes);
     if (st != WF_OK) return st;
     if (nbytes <= 0) return WF_OK;
+    if (t_staging && t_staging->base) {
+        const int64_t off = (t_staging->used + 255) / 256 * 256;
+        if (off + nbytes <= t_staging->size) {
+            std::memcpy(t_staging->base + off, host, (size_t)nbytes);
+            t_staging->used = off + nbytes;
+            return hip_check(hipMemcpyAsync(ptr, t_staging->base + off, (size_t)nbytes, hipMemcpyHostToDevice,
+                                            t_staging->stream),
+                             "staged upload");
+        }
+    }
     hipError_t e = hipMemcpy(ptr, host, (size_t)nbytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(WF_E_HIP, "hipMemcpy H2D: %s", hipGetErrorString(e));
     return WF_OK;
@@ -513,6 +525,41 @@ wf_status Model::init(const wf_geom* g, const float* m_dev, hipStream_t s) {
     if (st != WF_OK) return st;
     if ((st = d_scratch.alloc(256)) != WF_OK) return st;
     return set_m(m_dev, s);
+}
+
+wf_status Model::init_pending(const wf_geom* g, const float* m_dev, hipStream_t s, unsigned int* host3) {
+    if (!m_dev) return fail(WF_E_ARG, "m is NULL");
+    geom = *g;
+    half = g->space_order / 2;
+    L.init(g);
+    fd_weights(half, alpha);
+    WF_TRY_RT(d_m.alloc(L.npoints * 4));
+    WF_TRY_RT(d_kap.alloc(L.field_bytes()));
+    WF_TRY_RT(hip_check(launch_fill(d_kap.f(), d_kap.bytes / 4, 0.0f, s), "fill"));
+    std::vector<float> ex = eta_profile(g, 0);
+    std::vector<float> ey = g->ndim == 3 ? eta_profile(g, 1) : std::vector<float>(1, 0.0f);
+    std::vector<float> ez = eta_profile(g, g->ndim - 1);
+    WF_TRY_RT(upload_packed(d_eta_pack, {{&d_etax, ex.data(), (int64_t)ex.size() * 4},
+                                         {&d_etay, ey.data(), (int64_t)ey.size() * 4},
+                                         {&d_etaz, ez.data(), (int64_t)ez.size() * 4}}));
+    WF_TRY_RT(d_scratch.alloc(256));
+    WF_TRY_RT(use_stream(s));
+    WF_TRY_RT(hip_check(hipMemcpyAsync(d_m.f(), m_dev, (size_t)L.npoints * 4, hipMemcpyDeviceToDevice, s), "copy m"));
+    // min / max / invalid count of m, as refresh_m, read back without a wait
+    float* d3 = d_scratch.f();
+    WF_TRY_RT(hip_check(launch_fill(d3, 1, FLT_MAX, s), "init minmax"));
+    WF_TRY_RT(hip_check(launch_fill(d3 + 1, 2, 0.0f, s), "init minmax"));
+    WF_TRY_RT(hip_check(launch_minmax(d_m.f(), L.npoints, d3, s), "minmax"));
+    WF_TRY_RT(hip_check(hipMemcpyAsync(host3, d3, 3 * sizeof(unsigned int), hipMemcpyDeviceToHost, s), "read minmax"));
+    kap_dt = -1.0;
+    return WF_OK;
+}
+
+wf_status Model::finish_m(const unsigned int* host3) {
+    if (host3[2] != 0) return fail(WF_E_ARG, "m has %u values that are not positive and finite", host3[2]);
+    std::memcpy(&m_min, &host3[0], 4);
+    std::memcpy(&m_max, &host3[1], 4);
+    return WF_OK;
 }
 
 wf_status Model::use_stream(hipStream_t s) {

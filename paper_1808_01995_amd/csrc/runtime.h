@@ -52,6 +52,19 @@ struct ScratchRegion {
 void set_thread_scratch(ScratchRegion* r);
 bool thread_scratch_active();
 
+// Pinned host memory for the small uploads of one thread: while set, a
+// DevBuf::upload that fits copies its data here and queues an asynchronous
+// copy on `stream` instead of a synchronous one. The caller synchronises
+// `stream` before it resets `used`, frees the staging or uses the uploaded
+// buffers on another stream.
+struct PinnedStaging {
+    char* base = nullptr;
+    int64_t size = 0;
+    int64_t used = 0;
+    hipStream_t stream = nullptr;
+};
+void set_thread_staging(PinnedStaging* p);
+
 // Owned device allocation.
 struct DevBuf {
     void* ptr = nullptr;
@@ -65,7 +78,7 @@ struct DevBuf {
     ~DevBuf();
     void reset();
     wf_status alloc(int64_t nbytes);
-    wf_status upload(const void* host, int64_t nbytes);   // synchronous
+    wf_status upload(const void* host, int64_t nbytes);   // synchronous (asynchronous through a thread's PinnedStaging)
     float* f() const { return static_cast<float*>(ptr); }
     template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
@@ -187,6 +200,12 @@ struct Model : public wf_model {
 
     ~Model() override;
     wf_status init(const wf_geom* g, const float* m_dev, hipStream_t s);
+    // init without the two wavefields (a caller that keeps them elsewhere)
+    // and with the check of m left pending: its min, max and invalid count
+    // land in host3 (pinned) when `s` passes the copy; finish_m(host3)
+    // after that completes the init
+    wf_status init_pending(const wf_geom* g, const float* m_dev, hipStream_t s, unsigned int* host3);
+    wf_status finish_m(const unsigned int* host3);
     wf_status set_m(const float* m_dev, hipStream_t s);
     wf_status refresh_m(hipStream_t s);
     // the physical grid as a box [b0, b1) per layout axis (x, y, z; y = [0, 1) in 2D)
