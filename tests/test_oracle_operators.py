@@ -203,6 +203,21 @@ def test_damping_profile_and_dissipation(oracle_mod):
     assert np.all(np.diff(row[:nbl + 1]) < 0) and np.all(np.diff(row[-nbl - 1:]) > 0)
     emax = 3 * math.log(1e3) / (2 * nbl * 10.0 * 2.0)
     assert abs(row[0] - emax) < 1e-15
+    # the profile's exponent (quadratic in the depth d into the layer, the
+    # reading of the smooth profile): constant second differences over d =
+    # 0..nbl on both sides, equal to 2 emax / nbl^2, where a linear or cubic
+    # profile would give zero or linearly varying ones
+    for side in (row[:nbl + 1][::-1], row[-nbl - 1:]):
+        d2 = np.diff(side, 2)
+        assert np.allclose(d2, 2 * emax / nbl ** 2, rtol=1e-12, atol=0.0), d2
+    for wrong in (1, 3):   # the check rejects another exponent
+        r2 = o.damping_eta(shape_phys, nbl, (10.0, 10.0), 2.0, power=wrong)[:, nbl + 5]
+        assert not np.allclose(np.diff(r2[-nbl - 1:], 2), 2 * emax / nbl ** 2, rtol=1e-12, atol=0.0)
+    # separable: a node of a corner of the layer carries the sum of the two
+    # axes' values
+    c = nbl + 5
+    for i, j in ((0, 0), (2, eta.shape[1] - 1), (eta.shape[0] - 3, 1)):
+        assert abs(eta[i, j] - (eta[i, c] + eta[c, j])) <= 1e-15 * eta[i, j]
     # energy never increases with eta >= 0
     shape = eta.shape
     g = o.Grid(shape, (10.0, 10.0), 8)
