@@ -351,3 +351,73 @@ def test_resident_teams_equal_batched_launches_plain_propagator_and_oracle():
         d_ref = oracle.forward(og, r.m.cpu().numpy().astype(np.float64), eta, r.dt, r.nt, ps,
                                r.src_wav.cpu().numpy().astype(np.float64), pr)
         check_record(teams[i].cpu().numpy(), d_ref, label="resident team %dD order %d" % (nd, g.space_order))
+
+
+def _with_points(r, src_xyz, rec_xyz, seed):
+    """Replace a request's sources (Ricker wavelets with per-source scales)
+    and receivers."""
+    from synthetic import ricker
+    r.src_xyz = np.asarray(src_xyz, dtype=np.float64)
+    w = ricker(r.nt, r.dt, 10.0)[:, None] * np.linspace(1.0, 0.5, r.src_xyz.shape[0])[None, :]
+    r.src_wav = torch.from_numpy(w.astype(np.float32)).cuda()
+    r.rec_xyz = np.asarray(rec_xyz, dtype=np.float64)
+    r.rec_out = torch.empty((r.nt, r.rec_xyz.shape[0]), dtype=torch.float32, device="cuda")
+    return r
+
+
+def test_resident_team_edge_cases_equal_other_paths():
+    """Resident teams at the edges of what they take: 3D order 4 (512
+    threads) and order 16 (256 threads), 2D order 16, one- and two-sample
+    shots, three sources (one in the absorbing layer, one on the grid's last
+    node) with a receiver on that node; and a grid one node past the LDS limit
+    (142^2), which must go to the batched launches. Every record equals the
+    run with resident teams switched off and the plain propagator bit for bit;
+    the multi-source one also matches the oracle."""
+    import os
+    import oracle
+    from _harness import check_record
+    from paper_1808_01995_amd.serve import Server, build_request, run_one_shot_baseline, run_stream
+    specs = [({"ndim": 3, "n": 14, "space_order": 4, "steps": 80, "kind": "forward", "seed": 120}, 6),
+             ({"ndim": 3, "n": 6, "space_order": 16, "steps": 60, "kind": "forward", "seed": 121}, 8),
+             ({"ndim": 2, "n": 60, "space_order": 16, "steps": 90, "kind": "forward", "seed": 122}, 10),
+             ({"ndim": 2, "n": 101, "space_order": 4, "steps": 0, "kind": "forward", "seed": 123}, 20),
+             ({"ndim": 2, "n": 101, "space_order": 4, "steps": 1, "kind": "forward", "seed": 124}, 20),
+             ({"ndim": 2, "n": 70, "space_order": 8, "steps": 150, "kind": "forward", "seed": 125}, 10),
+             ({"ndim": 2, "n": 102, "space_order": 4, "steps": 60, "kind": "forward", "seed": 126}, 20)]
+    reqs = [build_request(sp, nbl=nbl) for sp, nbl in specs]
+    multi = reqs[5]
+    h, nbl = 10.0, 10
+    last = (70 - 1 + nbl) * h
+    _with_points(multi, [[345.0, 20.0], [-7.5 * h, 123.0], [last, last]],
+                 np.vstack([np.stack([np.linspace(0.0, 690.0, 40), np.full(40, 30.0)], 1), [[last, last]]]), 125)
+    srv = Server(hbm_budget_bytes=2 << 30, max_slots=16)
+    st = run_stream(srv, reqs)
+    paths = srv.paths()
+    srv.close()
+    assert st["failed"] == 0, [r.status for r in reqs]
+    assert paths == {"teams": len(reqs) - 1, "batched": 1, "workers": 0}, paths
+    teams = [r.rec_out.clone() for r in reqs]
+    os.environ["WAVEFD_TEAMS"] = "0"
+    try:
+        srv = Server(hbm_budget_bytes=2 << 30, max_slots=16)
+        for r in reqs:
+            r.rec_out.fill_(float("nan"))
+        st = run_stream(srv, reqs)
+        srv.close()
+    finally:
+        del os.environ["WAVEFD_TEAMS"]
+    assert st["failed"] == 0
+    base = run_one_shot_baseline(reqs)
+    for i, (r, (d, _)) in enumerate(zip(reqs, base["outputs"])):
+        assert torch.equal(teams[i], r.rec_out), i
+        assert torch.equal(teams[i], d), i
+    assert torch.count_nonzero(teams[3]) == 0 and teams[3].shape[0] == 1
+    g = multi.geom
+    shape = (g.n[0] + 2 * g.nbl, g.n[1] + 2 * g.nbl)
+    hh = (g.h[0], g.h[1])
+    d_ref = oracle.forward(oracle.Grid(shape, hh, g.space_order), multi.m.cpu().numpy().astype(np.float64),
+                           oracle.damping_eta((g.n[0], g.n[1]), g.nbl, hh, g.c_ref), multi.dt, multi.nt,
+                           oracle.sparse_points(multi.src_xyz, hh, g.nbl, shape),
+                           multi.src_wav.cpu().numpy().astype(np.float64),
+                           oracle.sparse_points(multi.rec_xyz, hh, g.nbl, shape))
+    check_record(teams[5].cpu().numpy(), d_ref, label="resident team, three sources")
