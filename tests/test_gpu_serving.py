@@ -421,3 +421,36 @@ def test_resident_team_edge_cases_equal_other_paths():
                            multi.src_wav.cpu().numpy().astype(np.float64),
                            oracle.sparse_points(multi.rec_xyz, hh, g.nbl, shape))
     check_record(teams[5].cpu().numpy(), d_ref, label="resident team, three sources")
+
+
+def test_every_path_at_once_equals_one_at_a_time():
+    """All three engine paths busy together: 48 tiny shots of 2D orders 4 /
+    8 / 12 and 3D order 8 on resident teams (several launches in flight), six
+    mid-size 2D grids on the batched launches, a 3D grid above the batching
+    limit and two gradients on the workers, submitted at once and then in a
+    second burst while the first still runs. Every record and gradient equals
+    the one-shot run bit for bit, and each path served what it should."""
+    from paper_1808_01995_amd.serve import Server, run_one_shot_baseline, run_stream
+    tiny = [{"ndim": 2, "n": 60 + 7 * (i % 5), "space_order": (4, 8, 12)[i % 3], "steps": 40 + 9 * (i % 7),
+             "kind": "forward", "seed": 400 + i} for i in range(40)]
+    tiny += [{"ndim": 3, "n": 4 + (i % 3), "space_order": 8, "steps": 30 + 5 * i, "kind": "forward",
+              "seed": 440 + i} for i in range(8)]
+    mid = [{"ndim": 2, "n": 180 + 40 * i, "space_order": (4, 8, 12)[i % 3], "steps": 50, "kind": "forward",
+            "seed": 460 + i} for i in range(6)]
+    heavy = [{"ndim": 3, "n": 176, "space_order": 8, "steps": 20, "kind": "forward", "seed": 470},
+             {"ndim": 2, "n": 90, "space_order": 8, "steps": 40, "kind": "gradient", "seed": 471, "perturb": 0.05},
+             {"ndim": 3, "n": 24, "space_order": 4, "steps": 30, "kind": "gradient", "seed": 472, "perturb": 0.05}]
+    specs = tiny[:24] + mid[:3] + heavy + tiny[24:] + mid[3:]
+    reqs = _build(specs, nbl=10)
+    arrivals = [0.0] * (24 + 3 + 3) + [0.004] * (24 + 3)
+    srv = Server(hbm_budget_bytes=24 << 30, max_slots=96)
+    st = run_stream(srv, reqs, arrivals)
+    paths = srv.paths()
+    srv.close()
+    assert st["failed"] == 0, [r.status for r in reqs]
+    assert paths == {"teams": 48, "batched": 6, "workers": 3}, paths
+    base = run_one_shot_baseline(reqs, 24 << 30)
+    for i, (r, (d, g)) in enumerate(zip(reqs, base["outputs"])):
+        assert torch.equal(r.rec_out, d), (i, specs[i])
+        if g is not None:
+            assert torch.equal(r.grad_out, g), (i, specs[i])
