@@ -26,6 +26,7 @@
 //   the bandwidth while evicting each other from the Infinity Cache (two
 //   concurrent 3D shots took 7 % longer than the same shots in turn).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <chrono>
 #include <condition_variable>
@@ -621,15 +622,43 @@ void wf_engine::batcher() {
 struct TeamLaunch {
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;      // recorded after the launch
-    TeamJob* host = nullptr;      // pinned table
+    TeamJob* host = nullptr;      // pinned: the table, then the error flag read back after the launch
     int cap = 0;
-    DevBuf dev;                   // the table, then the shot counter
+    DevBuf dev;                   // the table, the shot counter and error flag, barrier counters, exchange
     std::vector<EJob*> jobs;      // in flight
+    bool split = false;           // its shots are split over teams of work-groups
+    unsigned int* err_host() const { return reinterpret_cast<unsigned int*>(host + cap); }
 };
 
 namespace {
 
 constexpr int kTeamLaunches = 4;
+constexpr unsigned long long kTeamWaitTicks = 100000000ull;   // 1 s at 100 MHz: a barrier wait that long fails
+constexpr int kTeamMaxWidth = 8;
+constexpr int kTeamMaxPeriod = 8;
+
+// Work-groups per shot and updates between exchanges. A launch of few shots
+// splits each over up to kTeamMaxWidth work-groups (at most one per CU in
+// all), each owning at least max(8, M) planes; the period is as long as
+// every part's planes allow (period M <= planes owned), up to
+// kTeamMaxPeriod. WAVEFD_TEAM_WIDTH (1, 2, 4, 8) and WAVEFD_TEAM_PERIOD
+// override within those limits.
+void team_split(int n, int min_nx, int half, int cus, int* width, int* period) {
+    int w = 1;
+    while (w < kTeamMaxWidth && (int64_t)2 * w * n <= cus) w *= 2;
+    if (const char* e = std::getenv("WAVEFD_TEAM_WIDTH")) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8) w = v;
+    }
+    while (w > 1 && min_nx / w < std::max(half, 8)) w /= 2;
+    int k = w > 1 ? std::min(kTeamMaxPeriod, (min_nx / w) / half) : 1;
+    if (const char* e = std::getenv("WAVEFD_TEAM_PERIOD")) {
+        const int v = std::atoi(e);
+        if (v >= 1) k = std::min(k, v);
+    }
+    *width = w;
+    *period = std::max(1, k);
+}
 constexpr int64_t kTeamStagingBytes = (int64_t)8 << 20;   // pinned staging of the set-up uploads of a batch
 
 TeamJob team_job(const Model& md, const PointSet& src, const PointSet& rec, const wf_request& r,
@@ -692,35 +721,68 @@ wf_status team_increments(const Model& md, const PointSet& src, const wf_request
     return hip_check(launch_increments(ip, s), "increments");
 }
 
-// table of `jobs` into `L` (growing it), then the launch and its event
-wf_status team_launch(TeamLaunch& L, const std::vector<EJob*>& jobs, int ndim, int half, int cus) {
+// table of `jobs` into `L` (growing it), then the launch, the read-back of
+// its error flag and its event
+wf_status team_launch(TeamLaunch& L, const std::vector<EJob*>& jobs, int ndim, int half, int cus,
+                      bool split_ok) {
     const int n = (int)jobs.size();
+    int min_nx = INT_MAX;
+    int64_t max_plane = 0;   // float4 per x plane
+    for (const EJob* j : jobs) {
+        min_nx = std::min(min_nx, j->md->L.nx);
+        max_plane = std::max<int64_t>(max_plane, (int64_t)j->md->L.ny * ((j->md->L.nz + 3) / 4));
+    }
+    int width = 1, period = 1;
+    if (split_ok) team_split(n, min_nx, half, cus, &width, &period);
+    L.split = width > 1;
+    const int64_t stride = width > 1 ? (int64_t)2 * width * 2 * 2 * period * half * max_plane : 0;   // float4
+    const int64_t off_ctl = (int64_t)sizeof(TeamJob) * std::max(n, 256);
+    const int64_t off_cnt = off_ctl + 256;
+    const int64_t off_exch = (off_cnt + (int64_t)n * 128 + 255) / 256 * 256;
+    const int64_t need = off_exch + stride * 16 * n;
     if (n > L.cap) {
         if (L.host) (void)hipHostFree(L.host);
         L.host = nullptr;
         L.cap = 0;
-        L.dev.reset();
         const int cap = std::max(n, 256);
-        if (hipHostMalloc(reinterpret_cast<void**>(&L.host), sizeof(TeamJob) * cap) != hipSuccess) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&L.host), sizeof(TeamJob) * cap + 256) != hipSuccess) {
             L.host = nullptr;
             return fail(WF_E_NOMEM, "pinned team table");
         }
-        const wf_status st = L.dev.alloc((int64_t)sizeof(TeamJob) * cap + 256);
-        if (st != WF_OK) return st;
         L.cap = cap;
+    }
+    if (L.dev.bytes < need) {
+        const wf_status st = L.dev.alloc(need);
+        if (st != WF_OK) return st;
     }
     for (int i = 0; i < n; ++i) {
         const EJob& j = *jobs[(size_t)i];
         L.host[i] = team_job(*j.md, *j.ps_src, *j.ps_rec, j.rq, j.inc.f());
     }
+    char* base = L.dev.as<char>();
     TeamArgs a;
-    a.jobs = L.dev.as<TeamJob>();
-    a.next = reinterpret_cast<unsigned int*>(L.dev.as<char>() + sizeof(TeamJob) * L.cap);
+    a.jobs = reinterpret_cast<const TeamJob*>(base);
+    a.next = reinterpret_cast<unsigned int*>(base + off_ctl);
+    a.err = a.next + 1;
     a.njobs = n;
+    a.width = width;
+    a.period = period;
+    a.cnt = reinterpret_cast<unsigned int*>(base + off_cnt);
+    a.exch = reinterpret_cast<float4*>(base + off_exch);
+    a.exch_stride = stride;
+    a.limit = kTeamWaitTicks;
+    *L.err_host() = 0;
+    const int nteams = width > 1 ? std::min(n, std::max(1, cus / width)) : std::min(n, cus);
     wf_status st = hip_check(hipMemcpyAsync(L.dev.ptr, L.host, sizeof(TeamJob) * n, hipMemcpyHostToDevice, L.s),
                              "team table");
-    if (st == WF_OK) st = hip_check(launch_fill(reinterpret_cast<float*>(a.next), 1, 0.0f, L.s), "team counter");
-    if (st == WF_OK) st = hip_check(launch_team(a, ndim, half, std::min(n, cus), L.s), "team launch");
+    // shot counter, error flag and barrier counters start at zero
+    if (st == WF_OK)
+        st = hip_check(launch_fill(reinterpret_cast<float*>(a.next), (off_exch - off_ctl) / 4, 0.0f, L.s),
+                       "team counters");
+    if (st == WF_OK) st = hip_check(launch_team(a, ndim, half, nteams * width, L.s), "team launch");
+    if (st == WF_OK)
+        st = hip_check(hipMemcpyAsync(L.err_host(), a.err, sizeof(unsigned int), hipMemcpyDeviceToHost, L.s),
+                       "team error flag");
     if (st == WF_OK) st = hip_check(hipEventRecord(L.ev, L.s), "event");
     return st;
 }
@@ -824,7 +886,9 @@ void wf_engine::teams() {
                 if (L.jobs.empty()) continue;
                 const hipError_t q = hipEventQuery(L.ev);
                 if (q == hipErrorNotReady) continue;
-                const wf_status st = q == hipSuccess ? WF_OK : hip_check(q, "team launch");
+                wf_status st = q == hipSuccess ? WF_OK : hip_check(q, "team launch");
+                if (st == WF_OK && *L.err_host() != 0)
+                    st = fail(WF_E_STATE, "a resident team's barrier wait timed out");
                 std::vector<EJob*> done_jobs;
                 done_jobs.swap(L.jobs);
                 for (EJob* j : done_jobs) finish(j, st);
@@ -839,7 +903,11 @@ void wf_engine::teams() {
                 std::vector<EJob*> group, rest;
                 for (EJob* j : backlog) (j->md->geom.ndim == ndim && j->md->half == half ? group : rest).push_back(j);
                 backlog.swap(rest);
-                const wf_status st = team_launch(*L, group, ndim, half, cus);
+                // one split launch at a time: its teams wait only for their
+                // own work-groups, which wait only for finite kernels
+                bool split_ok = true;
+                for (const TeamLaunch& c : launches) split_ok = split_ok && (c.jobs.empty() || !c.split);
+                const wf_status st = team_launch(*L, group, ndim, half, cus, split_ok);
                 if (st != WF_OK) {
                     (void)hipStreamSynchronize(L->s);
                     for (EJob* j : group) finish(j, st);

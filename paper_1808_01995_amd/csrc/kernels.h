@@ -106,9 +106,12 @@ hipError_t launch_step_batch(const BatchJob* jobs_dev, int njobs, int total_bloc
 // work-group's LDS (the serving engine's resident teams): each work-group of
 // a launch takes a shot from the launch's table, steps it to the end with
 // only work-group barriers (the fields never leave LDS), writes its record and
-// takes the next. The source increments are made beforehand by
-// launch_increments over the point set's node tables. Results equal
-// wf_forward's bit for bit (the same arithmetic in the same order).
+// takes the next; or, for few shots, each shot split over a team of W
+// work-groups that recompute their neighbours' nearest planes for `period`
+// updates and then exchange boundary planes through global memory with one
+// barrier. The source increments are made beforehand by launch_increments
+// over the point set's node tables. Results equal wf_forward's bit for bit
+// (the same arithmetic in the same order).
 constexpr int kTeamThreads = 1024;
 constexpr int kTeamFieldFloats = 40640;   // two fields of nx * ny * round4(nz) floats
 struct TeamJob {
@@ -128,8 +131,15 @@ struct TeamJob {
 };
 struct TeamArgs {
     const TeamJob* jobs;        // device memory, njobs shots of one (ndim, half)
-    unsigned int* next;         // device memory, 0 at the launch
+    unsigned int* next;         // device memory, 0 at the launch (width 1)
     int njobs;
+    int width;                  // work-groups per shot: 1, or W > 1 (the launch is teams x W work-groups)
+    int period;                 // width > 1: updates between exchanges (every part owns >= period M planes)
+    float4* exch;               // width > 1: boundary planes, exch_stride float4 per shot
+    int64_t exch_stride;        //   (2 x W x 2 x 2 x period M planes of the shot's plane size)
+    unsigned int* cnt;          // width > 1: one barrier counter per shot, 32 apart, 0 at the launch
+    unsigned int* err;          // 0 at the launch; nonzero after it: a barrier wait timed out
+    unsigned long long limit;   // longest barrier wait (s_memrealtime ticks, 100 MHz)
 };
 // A grid fits a team when both fields (z padded to 4) fit kTeamFieldFloats.
 bool team_fits(int64_t nx, int64_t ny, int64_t nz);

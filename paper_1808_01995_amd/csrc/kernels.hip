@@ -493,13 +493,57 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 // Threads of a team: as many as keep every register of a thread's node
 // column (the x ring, the z window, the plane ahead) without spilling:
 // 1024 (16 waves, 128 VGPRs) for the 2D order-4 stencil, 256 for the 3D
-// order-16 one, 512 otherwise.
+// ones of order 12 and above, 512 otherwise.
 __host__ __device__ constexpr int team_threads(bool d3, int m) {
-    return d3 ? (m >= 8 ? 256 : 512) : (m <= 2 ? kTeamThreads : 512);
+    return d3 ? (m >= 6 ? 256 : 512) : (m <= 2 ? kTeamThreads : 512);
 }
 
-template <bool D3, int M>
-__device__ void team_run(const TeamJob& J, float* F) {
+// How a shot is split over the work-groups of a team. Work-group w of W owns
+// planes [w nx / W, (w + 1) nx / W) and holds K M more on either side (its
+// window): for K updates it recomputes the part of its neighbours' planes
+// that its own planes' stencils reach, on a window that narrows by M planes
+// per update, and after every K updates the work-groups exchange K M
+// boundary planes of the two newest fields through global memory with one
+// barrier. The recomputed planes get the owners' bits (the same arithmetic
+// on the same values), so the split changes no result. W = 1: one
+// work-group holds the whole grid.
+struct TeamPart {
+    int w, W, K;
+    float4* exch;               // [2 parities][W][2 sides][2 fields][K M planes][plane] (W > 1)
+    unsigned int* cnt;          // the team's barrier counter (W > 1)
+    unsigned int* err;          // raised when a barrier wait times out
+    unsigned long long limit;   // longest barrier wait (s_memrealtime ticks, 100 MHz)
+};
+
+// Barrier of a team's work-groups: thread 0 arrives (release) and waits until
+// `target` arrivals (then acquire). Every wait is bounded: on a timeout, or
+// an error raised by another work-group, it raises the error and returns
+// false, and the caller leaves.
+__device__ bool team_sync(const TeamPart& tp, unsigned int target) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __hip_atomic_fetch_add(tp.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(tp.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(tp.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                __builtin_amdgcn_s_memrealtime() - t0 > tp.limit) {
+                __hip_atomic_fetch_add(tp.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <bool D3, int M, bool SPLIT>
+__device__ bool team_run(const TeamJob& J, float* F, const TeamPart& tp) {
     constexpr int T = team_threads(D3, M);
     constexpr int P = (M + 3) & ~3;
     constexpr int HZ = P / 4;
@@ -521,20 +565,26 @@ __device__ void team_run(const TeamJob& J, float* F) {
     const float* __restrict__ etaz = J.etaz;
     const int64_t sxk = J.sx, syk = J.sy;
     const int nzv = (nz + 3) / 4;
-    const int npts = nx * ny * nzv * 4;
+    const int psx = ny * nzv;   // float4 per x plane
+    // this work-group's planes [xs, xe) and the window [lo, hi) it holds
+    const int W = SPLIT ? tp.W : 1;
+    const int wr = SPLIT ? tp.w : 0;
+    const int K = SPLIT ? tp.K : 1;
+    const int KM = SPLIT ? K * M : 0;
+    const int xs = wr * nx / W, xe = (wr + 1) * nx / W;
+    const int lo = max(0, xs - KM), hi = min(nx, xe + KM);
+    const int npts = (hi - lo) * psx * 4;
     float* A = F;          // u^n
     float* B = F + npts;   // u^{n-1}, overwritten by u^{n+1}
     for (int i = tid; i < 2 * npts; i += T) F[i] = 0.0f;
-    // work items: a (y, z/4) column times a chunk of x planes; the chunks
-    // split nx as evenly as possible (sizes differ by at most one plane)
-    const int ncol = ny * nzv;
-    const int nch = max(1, min(T / ncol, nx));
-    // pitched offset -> dense LDS index, by float reciprocals (a grid that
-    // fits has fewer than 2^24 pitched elements, so the quotient estimate is
-    // off by at most one, which the remainder test corrects)
+    const int ncol = psx;   // work items: a (y, z/4) column times a chunk of planes
+    // pitched offset -> plane and dense index in the window, by float
+    // reciprocals (a grid that fits has fewer than 2^24 pitched elements,
+    // so the quotient estimate is off by at most one, which the remainder
+    // test corrects)
     const int sxi = (int)J.sx, syi = (int)J.sy;
     const float rsx = 1.0f / (float)sxi, rsy = 1.0f / (float)syi;
-    auto dense = [&](int64_t o64) -> int {
+    auto dense = [&](int64_t o64, int& xo) -> int {
         const int o = (int)o64;
         int x = (int)((float)o * rsx);
         int r = o - x * sxi;
@@ -554,30 +604,41 @@ __device__ void team_run(const TeamJob& J, float* F) {
             ++y;
             z -= syi;
         }
-        return (x * ny + y) * (nzv * 4) + z;
+        xo = x;
+        return ((x - lo) * ny + y) * (nzv * 4) + z;
     };
     // the job's constant tables, converted once: the first receiver of each
     // thread (2D; 3D receivers are many and their registers are needed by
-    // the stencil) and the first source node
+    // the stencil) and the first source node. A receiver belongs to the
+    // work-group that owns its cell's first corner (the other corners lie in
+    // its window); a source node is added by every work-group that computes
+    // its plane, so that recomputed planes match their owner's.
     int rd[KS];
     float rw[KS];
-    const bool rcache = !D3 && tid < J.nrec;
-    if (rcache) {
+    bool rown = false;
+    if (!D3 && tid < J.nrec) {
+        int xc = 0;
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            rd[k] = dense(J.smp_off[(int64_t)tid * KS + k]);
+            int xk;
+            rd[k] = dense(J.smp_off[(int64_t)tid * KS + k], xk);
+            if (k == 0) xc = xk;
             rw[k] = J.smp_w[(int64_t)tid * KS + k];
         }
+        rown = !SPLIT || (xc >= xs && xc < xe);
     }
-    const int nd = tid < J.nnodes ? dense(J.noff[tid]) : 0;
+    int nd = 0, ndx = 0;
+    if (tid < J.nnodes) nd = dense(J.noff[tid], ndx);
     __syncthreads();
     auto sample = [&](const float* U, int row) {
         int i = tid;
-        if (rcache) {
-            float acc = 0.0f;
+        if (!D3 && i < J.nrec) {
+            if (rown) {
+                float acc = 0.0f;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) acc = fmaf(rw[k], U[rd[k]], acc);
-            J.rec[(int64_t)row * J.nrec + i] = acc;
+                for (int k = 0; k < KS; ++k) acc = fmaf(rw[k], U[rd[k]], acc);
+                J.rec[(int64_t)row * J.nrec + i] = acc;
+            }
             i += T;
         }
         for (; i < J.nrec; i += T) {
@@ -588,24 +649,40 @@ __device__ void team_run(const TeamJob& J, float* F) {
                 so[k] = (int)J.smp_off[(int64_t)i * KS + k];
                 sw[k] = J.smp_w[(int64_t)i * KS + k];
             }
+            int xc = 0;
+            int di[KS];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                int xk;
+                di[k] = dense(so[k], xk);
+                if (k == 0) xc = xk;
+            }
+            if (SPLIT && (xc < xs || xc >= xe)) continue;
             float acc = 0.0f;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) acc = fmaf(sw[k], U[dense(so[k])], acc);
+            for (int k = 0; k < KS; ++k) acc = fmaf(sw[k], U[di[k]], acc);
             J.rec[(int64_t)row * J.nrec + i] = acc;
         }
     };
-    const int psx = ny * nzv;   // float4 per x plane
     for (int n = 0; n + 1 < J.nt; ++n) {
-        // this step's increment of the thread's source node, used after the
-        // update (its latency hides behind it)
-        const float incv = tid < J.nnodes ? J.inc[(int64_t)n * J.nnodes + tid] : 0.0f;
+        // planes computed this update: the window narrowed by M per update
+        // since the last exchange on every side that faces a neighbour
+        const int j = SPLIT ? n % K : 0;
+        const int clo = lo == 0 ? 0 : lo + (j + 1) * M;
+        const int chi = hi == nx ? nx : hi - (j + 1) * M;
+        const int ncomp = chi - clo;
+        const int nch = max(1, min(T / ncol, ncomp));
+        // this update's increment of the thread's source node, used after
+        // the update (its latency hides behind it)
+        const bool inj = tid < J.nnodes && (!SPLIT || (ndx >= clo && ndx < chi));
+        const float incv = inj ? J.inc[(int64_t)n * J.nnodes + tid] : 0.0f;
         sample(A, n);
         const float4* __restrict__ A4 = reinterpret_cast<const float4*>(A);
         float4* __restrict__ B4 = reinterpret_cast<float4*>(B);
         for (int item = tid; item < ncol * nch; item += T) {
             const int col = item % ncol, ch = item / ncol;
             const int y = col / nzv, zv = col - y * nzv, z = 4 * zv;
-            const int x0 = ch * nx / nch, x1 = (ch + 1) * nx / nch;
+            const int x0 = clo + ch * ncomp / nch, x1 = clo + (ch + 1) * ncomp / nch;
             if (x0 >= x1) continue;
             const int cb = y * nzv + zv;   // the column in a plane (float4)
             // which z and y neighbour columns lie inside the grid (outside: zero)
@@ -614,19 +691,20 @@ __device__ void team_run(const TeamJob& J, float* F) {
             for (int k = 0; k < 2 * HZ + 1; ++k) zok[k] = zv - HZ + k >= 0 && zv - HZ + k < nzv;
             bool ylo[M + 1], yhi[M + 1];
 #pragma unroll
-            for (int j = 1; j <= M; ++j) {
-                ylo[j] = D3 && y - j >= 0;
-                yhi[j] = D3 && y + j < ny;
+            for (int jj = 1; jj <= M; ++jj) {
+                ylo[jj] = D3 && y - jj >= 0;
+                yhi[jj] = D3 && y + jj < ny;
             }
             // x ring: planes x - M .. x + M of the column, and x + M + 1
-            // loaded a plane ahead; the walk is unrolled by the ring length,
-            // so every slot index is a constant
+            // loaded a plane ahead (planes outside the window are outside the
+            // grid: zero); the walk is unrolled by the ring length, so every
+            // slot index is a constant
             constexpr int NR = 2 * M + 2;
             float4 r[NR];
 #pragma unroll
             for (int i = 0; i < 2 * M + 1; ++i) {
                 const int xx = x0 - M + i;
-                r[i] = xx >= 0 && xx < nx ? A4[xx * psx + cb] : zero4();
+                r[i] = xx >= lo && xx < hi ? A4[(xx - lo) * psx + cb] : zero4();
             }
             float eyz[4];
 #pragma unroll
@@ -644,35 +722,35 @@ __device__ void team_run(const TeamJob& J, float* F) {
                     const int x = xg + ph;
                     if (x < x1) {
                         const int xn = x + M + 1;
-                        r[(ph + 2 * M + 1) % NR] = xn < nx ? A4[xn * psx + cb] : zero4();
+                        r[(ph + 2 * M + 1) % NR] = xn < hi ? A4[(xn - lo) * psx + cb] : zero4();
                         if (x + 1 < x1) {
                             kq[(ph + 1) % 2] = ld4(kcol + (int64_t)(x + 1) * sxk);
                             eq[(ph + 1) % 2] = etax[x + 1];
                         }
                         const float4 kp = kq[ph % 2];
                         const float ex = eq[ph % 2];
-                        const int pc = x * psx + cb;
+                        const int pc = (x - lo) * psx + cb;
                         const float4 c = r[(ph + M) % NR];
                         float lap[4];
 #pragma unroll
                         for (int i = 0; i < 4; ++i) lap[i] = c0 * comp(c, i);
 #pragma unroll
-                        for (int j = 1; j <= M; ++j) {
-                            const float4 a = r[(ph + M - j) % NR], b = r[(ph + M + j) % NR];
-                            lap[0] = fmaf(wx[j], a.x + b.x, lap[0]);
-                            lap[1] = fmaf(wx[j], a.y + b.y, lap[1]);
-                            lap[2] = fmaf(wx[j], a.z + b.z, lap[2]);
-                            lap[3] = fmaf(wx[j], a.w + b.w, lap[3]);
+                        for (int jj = 1; jj <= M; ++jj) {
+                            const float4 a = r[(ph + M - jj) % NR], b = r[(ph + M + jj) % NR];
+                            lap[0] = fmaf(wx[jj], a.x + b.x, lap[0]);
+                            lap[1] = fmaf(wx[jj], a.y + b.y, lap[1]);
+                            lap[2] = fmaf(wx[jj], a.z + b.z, lap[2]);
+                            lap[3] = fmaf(wx[jj], a.w + b.w, lap[3]);
                         }
                         if (D3) {
 #pragma unroll
-                            for (int j = 1; j <= M; ++j) {
-                                const float4 a = ylo[j] ? A4[pc - j * nzv] : zero4();
-                                const float4 b = yhi[j] ? A4[pc + j * nzv] : zero4();
-                                lap[0] = fmaf(wy[j], a.x + b.x, lap[0]);
-                                lap[1] = fmaf(wy[j], a.y + b.y, lap[1]);
-                                lap[2] = fmaf(wy[j], a.z + b.z, lap[2]);
-                                lap[3] = fmaf(wy[j], a.w + b.w, lap[3]);
+                            for (int jj = 1; jj <= M; ++jj) {
+                                const float4 a = ylo[jj] ? A4[pc - jj * nzv] : zero4();
+                                const float4 b = yhi[jj] ? A4[pc + jj * nzv] : zero4();
+                                lap[0] = fmaf(wy[jj], a.x + b.x, lap[0]);
+                                lap[1] = fmaf(wy[jj], a.y + b.y, lap[1]);
+                                lap[2] = fmaf(wy[jj], a.z + b.z, lap[2]);
+                                lap[3] = fmaf(wy[jj], a.w + b.w, lap[3]);
                             }
                         }
                         {
@@ -685,8 +763,8 @@ __device__ void team_run(const TeamJob& J, float* F) {
 #pragma unroll
                             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                                for (int j = 1; j <= M; ++j)
-                                    lap[i] = fmaf(wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+                                for (int jj = 1; jj <= M; ++jj)
+                                    lap[i] = fmaf(wz[jj], w[P + i - jj] + w[P + i + jj], lap[i]);
                         }
                         const float4 uo = B4[pc];
                         float4 o;
@@ -702,9 +780,51 @@ __device__ void team_run(const TeamJob& J, float* F) {
             }
         }
         __syncthreads();
-        // q^n into u^{n+1}: one thread per source node
-        if (tid < J.nnodes) B[nd] += incv;
-        for (int k = tid + T; k < J.nnodes; k += T) B[dense(J.noff[k])] += J.inc[(int64_t)n * J.nnodes + k];
+        // q^n into u^{n+1}: one thread per source node in the planes computed
+        if (inj) B[nd] += incv;
+        for (int k = tid + T; k < J.nnodes; k += T) {
+            int xk;
+            const int d = dense(J.noff[k], xk);
+            if (!SPLIT || (xk >= clo && xk < chi)) B[d] += J.inc[(int64_t)n * J.nnodes + k];
+        }
+        if (SPLIT && (n + 1) % K == 0) {
+            // u^{n+1} (B) and u^n (A) are now valid on the owned planes (and
+            // u^n M planes beyond): exchange K M boundary planes of both with
+            // the neighbours, double-buffered by exchange parity, so one
+            // barrier per exchange separates a write from the reads of the
+            // same buffer
+            __syncthreads();
+            const int e = (n + 1) / K;
+            const int slab = KM * psx;
+            float4* base = tp.exch + (int64_t)((e & 1) * W) * 4 * slab;
+            float4* mine = base + (int64_t)wr * 4 * slab;   // [side][field][slab]
+            float4* A4w = reinterpret_cast<float4*>(A);
+            for (int i = tid; i < slab; i += T) {
+                const int pl = i / psx, c = i - pl * psx;
+                if (wr > 0) {
+                    mine[i] = B4[(xs + pl - lo) * psx + c];
+                    mine[slab + i] = A4w[(xs + pl - lo) * psx + c];
+                }
+                if (wr < W - 1) {
+                    mine[2 * slab + i] = B4[(xe - KM + pl - lo) * psx + c];
+                    mine[3 * slab + i] = A4w[(xe - KM + pl - lo) * psx + c];
+                }
+            }
+            if (!team_sync(tp, (unsigned int)e * (unsigned int)W)) return false;
+            const float4* left = base + (int64_t)(wr - 1) * 4 * slab + 2 * slab;   // its side 1
+            const float4* right = base + (int64_t)(wr + 1) * 4 * slab;             // its side 0
+            for (int i = tid; i < slab; i += T) {
+                const int pl = i / psx, c = i - pl * psx;
+                if (wr > 0) {
+                    B4[(xs - KM + pl - lo) * psx + c] = left[i];
+                    A4w[(xs - KM + pl - lo) * psx + c] = left[slab + i];
+                }
+                if (wr < W - 1) {
+                    B4[(xe + pl - lo) * psx + c] = right[i];
+                    A4w[(xe + pl - lo) * psx + c] = right[slab + i];
+                }
+            }
+        }
         __syncthreads();
         float* t = A;
         A = B;
@@ -713,8 +833,13 @@ __device__ void team_run(const TeamJob& J, float* F) {
     if (J.nt > 1) {
         sample(A, J.nt - 1);
     } else {
-        for (int i = tid; i < J.nrec; i += T) J.rec[i] = 0.0f;
+        for (int i = tid; i < J.nrec; i += T) {
+            int xc;
+            (void)dense(J.smp_off[(int64_t)i * KS], xc);
+            if (!SPLIT || (xc >= xs && xc < xe)) J.rec[i] = 0.0f;
+        }
     }
+    return true;
 }
 
 __device__ inline bool team_fits_dev(int nx, int ny, int nz) {
@@ -725,22 +850,47 @@ __device__ inline bool team_fits_dev(int nx, int ny, int nz) {
 // (one counter in device memory, zero at the launch), each stepping its shot
 // to the end in LDS before it takes the next. The job is read from the table
 // with a uniform index, so its scalars live in scalar registers.
-template <bool D3, int M>
+// A launch of resident teams. Width 1: work-groups take the launch's shots in
+// order (one counter in device memory, zero at the launch), each stepping its
+// shot to the end in LDS before it takes the next. Width W > 1: work-groups
+// t W .. t W + W - 1 form team t, which steps shots t, t + teams, ... split
+// over its W work-groups. The job is read from the table with a uniform
+// index, so its scalars live in scalar registers.
+template <bool D3, int M, bool SPLIT>
 __global__ void __launch_bounds__(team_threads(D3, M), 1) k_team(const TeamArgs a) {
     __shared__ __attribute__((aligned(16))) float F[kTeamFieldFloats];
     __shared__ int s_j;
     const TeamJob* __restrict__ jobs = a.jobs;
-    for (;;) {
-        if (threadIdx.x == 0) s_j = (int)atomicAdd(a.next, 1u);
-        __syncthreads();
-        const int j = __builtin_amdgcn_readfirstlane(s_j);
-        __syncthreads();   // s_j is rewritten for the next shot
-        if (j >= a.njobs) return;   // uniform
-        const TeamJob& J = jobs[j];
-        // the host groups shots by (ndim, half) and admits only grids that
-        // fit; a table entry that does not is skipped rather than overrun LDS
-        if (J.ndim == (D3 ? 3 : 2) && J.half == M && team_fits_dev(J.nx, J.ny, J.nz)) team_run<D3, M>(J, F);
-        __syncthreads();   // F is cleared for the next shot
+    const int W = SPLIT ? a.width : 1;
+    auto valid = [&](const TeamJob& J) {
+        // the host groups shots by (ndim, half), admits only grids that fit
+        // and splits a grid only where every part keeps at least K M planes;
+        // a table entry that does not hold is skipped rather than overrun LDS
+        return J.ndim == (D3 ? 3 : 2) && J.half == M && team_fits_dev(J.nx, J.ny, J.nz) &&
+               (!SPLIT || (a.period >= 1 && J.nx / W >= a.period * M));
+    };
+    if (!SPLIT) {
+        const TeamPart tp{0, 1, 1, nullptr, nullptr, a.err, a.limit};
+        for (;;) {
+            if (threadIdx.x == 0) s_j = (int)atomicAdd(a.next, 1u);
+            __syncthreads();
+            const int j = __builtin_amdgcn_readfirstlane(s_j);
+            __syncthreads();   // s_j is rewritten for the next shot
+            if (j >= a.njobs) return;   // uniform
+            const TeamJob& J = jobs[j];
+            if (valid(J)) (void)team_run<D3, M, false>(J, F, tp);
+            __syncthreads();   // F is cleared for the next shot
+        }
+    } else {
+        const int team = blockIdx.x / W, nteams = gridDim.x / W;
+        if (team >= nteams) return;
+        for (int j = team; j < a.njobs; j += nteams) {
+            const TeamJob& J = jobs[j];
+            const TeamPart tp{(int)(blockIdx.x % W), W, a.period, a.exch + (int64_t)j * a.exch_stride,
+                              a.cnt + (int64_t)j * 32, a.err, a.limit};
+            if (valid(J) && !team_run<D3, M, true>(J, F, tp)) return;   // a barrier timed out
+            __syncthreads();
+        }
     }
 }
 
@@ -1115,17 +1265,17 @@ bool team_fits(int64_t nx, int64_t ny, int64_t nz) {
     return nx > 0 && ny > 0 && nz > 0 && nx * ny * ((nz + 3) / 4 * 4) * 2 <= kTeamFieldFloats;
 }
 
-template <bool D3>
+template <bool D3, bool SPLIT>
 hipError_t launch_team_d(const TeamArgs& a, int half, int nwg, hipStream_t s) {
     const dim3 g(nwg);
     switch (half) {
-        case 2: hipLaunchKernelGGL((k_team<D3, 2>), g, dim3(team_threads(D3, 2)), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_team<D3, 3>), g, dim3(team_threads(D3, 3)), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_team<D3, 4>), g, dim3(team_threads(D3, 4)), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_team<D3, 5>), g, dim3(team_threads(D3, 5)), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_team<D3, 6>), g, dim3(team_threads(D3, 6)), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_team<D3, 7>), g, dim3(team_threads(D3, 7)), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_team<D3, 8>), g, dim3(team_threads(D3, 8)), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_team<D3, 2, SPLIT>), g, dim3(team_threads(D3, 2)), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_team<D3, 3, SPLIT>), g, dim3(team_threads(D3, 3)), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_team<D3, 4, SPLIT>), g, dim3(team_threads(D3, 4)), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_team<D3, 5, SPLIT>), g, dim3(team_threads(D3, 5)), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_team<D3, 6, SPLIT>), g, dim3(team_threads(D3, 6)), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_team<D3, 7, SPLIT>), g, dim3(team_threads(D3, 7)), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_team<D3, 8, SPLIT>), g, dim3(team_threads(D3, 8)), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1133,7 +1283,11 @@ hipError_t launch_team_d(const TeamArgs& a, int half, int nwg, hipStream_t s) {
 
 hipError_t launch_team(const TeamArgs& a, int ndim, int half, int nwg, hipStream_t s) {
     if (nwg <= 0) return hipSuccess;
-    return ndim == 3 ? launch_team_d<true>(a, half, nwg, s) : launch_team_d<false>(a, half, nwg, s);
+    if (a.width > 1) {
+        if (nwg % a.width != 0 || a.period < 1) return hipErrorInvalidValue;
+        return ndim == 3 ? launch_team_d<true, true>(a, half, nwg, s) : launch_team_d<false, true>(a, half, nwg, s);
+    }
+    return ndim == 3 ? launch_team_d<true, false>(a, half, nwg, s) : launch_team_d<false, false>(a, half, nwg, s);
 }
 
 hipError_t launch_inject(const InjectParams& p, hipStream_t s) {
