@@ -454,3 +454,51 @@ def test_every_path_at_once_equals_one_at_a_time():
         assert torch.equal(r.rec_out, d), (i, specs[i])
         if g is not None:
             assert torch.equal(r.grad_out, g), (i, specs[i])
+
+
+def test_split_teams_equal_batched_launches_for_every_width_and_period():
+    """Shots split over teams of W work-groups that exchange boundary planes
+    every K updates (W = 2 / 4 / 8, K = 1 / 3 / as long as the parts allow,
+    forced through WAVEFD_TEAM_WIDTH / WAVEFD_TEAM_PERIOD): 2D orders 4 and 8
+    with sources and receivers across the part boundaries and 3D order 8
+    records equal the batched launches bit for bit."""
+    import os
+    from paper_1808_01995_amd.serve import Server, build_request, run_stream
+    specs = [({"ndim": 2, "n": 101, "space_order": 4, "steps": 70, "kind": "forward", "seed": 500}, 20),
+             ({"ndim": 2, "n": 90, "space_order": 8, "steps": 55, "kind": "forward", "seed": 501}, 12),
+             ({"ndim": 3, "n": 6, "space_order": 8, "steps": 40, "kind": "forward", "seed": 502}, 10)]
+    reqs = [build_request(sp, nbl=nbl) for sp, nbl in specs]
+    # sources on either side of the part boundaries of the 2D grids
+    h = 10.0
+    for r, (sp, nbl) in zip(reqs[:2], specs[:2]):
+        n = sp["n"]
+        last = (n - 1) * h
+        xs = np.array([0.13, 0.249, 0.376, 0.5, 0.626, 0.751, 0.874]) * (n + 2 * nbl) * h - nbl * h
+        _with_points(r, np.stack([xs, np.full(xs.size, 35.0)], 1),
+                     np.stack([np.linspace(-nbl * h, last + nbl * h, 97), np.full(97, 25.0)], 1), 0)
+    os.environ["WAVEFD_TEAMS"] = "0"
+    try:
+        srv = Server(hbm_budget_bytes=2 << 30, max_slots=8)
+        st = run_stream(srv, reqs)
+        srv.close()
+    finally:
+        del os.environ["WAVEFD_TEAMS"]
+    assert st["failed"] == 0
+    ref = [r.rec_out.clone() for r in reqs]
+    for w in ("2", "4", "8"):
+        for k in ("1", "3", "64"):
+            os.environ["WAVEFD_TEAM_WIDTH"], os.environ["WAVEFD_TEAM_PERIOD"] = w, k
+            try:
+                srv = Server(hbm_budget_bytes=2 << 30, max_slots=8)
+                for r in reqs:
+                    r.rec_out.fill_(float("nan"))
+                for r in reqs:   # one at a time: each launch may split
+                    st = run_stream(srv, [r])
+                    assert st["failed"] == 0, (w, k)
+                paths = srv.paths()
+                srv.close()
+            finally:
+                del os.environ["WAVEFD_TEAM_WIDTH"], os.environ["WAVEFD_TEAM_PERIOD"]
+            assert paths["teams"] == len(reqs), paths
+            for i, r in enumerate(reqs):
+                assert torch.equal(r.rec_out, ref[i]), (w, k, i)
