@@ -451,9 +451,12 @@ wf_status wf_engine_stats(const wf_engine* engine, int64_t* queued, int64_t* run
 /* Completed requests by the path that ran them (any pointer may be NULL):
  * forward shots whose two wavefields fit one work-group's LDS (z padded to
  * 4, at most 40 640 floats for both: e.g. 141 x 141 in 2D, 26^3 in 3D) run
- * as resident teams, each work-group of a launch stepping a whole request
- * in LDS with only work-group barriers (requests of one dimension and order
- * that are set up together share a launch; up to 4 launches run at once);
+ * as resident teams, a work-group stepping a whole request in LDS with only
+ * work-group barriers, or, when a launch holds few requests, each split
+ * over up to 8 work-groups that recompute their neighbours' nearest planes
+ * and exchange boundary planes every few updates (requests of one dimension
+ * and order that are set up together share a launch; up to 4 launches run
+ * at once);
  * other forward shots of at most 5 M nodes share batched step launches; the
  * rest, and every gradient, run on worker streams. Resident teams are on by
  * default; WAVEFD_TEAMS=0 in the environment at engine creation sends their
