@@ -130,8 +130,9 @@ wf_status wf_model_set_m(wf_model* model, const float* m_dev, void* stream);
  * device memory again costs seconds). */
 int64_t wf_model_bytes(const wf_model* model);
 
-/* Free the model's cached gradient workspace; the next gradient call
- * allocates it again. Synchronises the model's device work. */
+/* Free the model's cached gradient workspace and the second pair of
+ * wavefields of the two-update forward loop; the next call that needs them
+ * allocates them again. Synchronises the model's device work. */
 wf_status wf_model_trim(wf_model* model);
 
 /* Validation aid. Outside the computational grid the wavefield is zero
@@ -179,6 +180,24 @@ wf_status wf_validate_enable(int on);
  * on at start-up when the environment sets WAVEFD_GRAPH=1. Captured loops are
  * kept while it is off and used again once it is switched back on. */
 wf_status wf_graph_enable(int on);
+
+/* Process-wide mode for running the time loop of wf_forward on 3D models of
+ * space order 4 or 8 two updates (eq. eulerfwd with the damping of eq.
+ * fdWE-abc, applied twice) per kernel launch: the launch reads u^n, u^{n-1}
+ * and kappa once and writes u^{n+1} and u^{n+2}, 20 bytes per node for two
+ * updates instead of 32 (the update is bound by memory traffic, Section
+ * "Performance"), at the price of recomputing u^{n+1} on a margin around
+ * every tile. 0: one update per launch; 1 (the default): two where that was
+ * measured faster (space order 4 on grids of at least 8e7 nodes); 2: two
+ * wherever compiled (orders 4 and 8). The environment's WAVEFD_TWO_STEP=0 or
+ * =2 sets the mode at start-up. Records, saved fields and the final fields
+ * are the same bits in every mode. Such a loop keeps a second pair of
+ * wavefields in the model (counted by wf_model_bytes, freed by
+ * wf_model_trim); calls made through the serving engine or the
+ * allocation-free entry point keep one update per launch, and so does a loop
+ * whose sources crowd a block beyond what it can stage. Other modes:
+ * WF_E_ARG. */
+wf_status wf_two_step_enable(int mode);
 
 /* Free the model and everything it holds. Synchronises its device work. */
 wf_status wf_model_destroy(wf_model* model);
@@ -337,8 +356,12 @@ int64_t wf_revolve_schedule(int64_t steps, int snaps, int32_t* kind, int64_t* at
 #define WF_KERNEL_SAMPLE  2   /* sparse interpolation                          */
 #define WF_KERNEL_STEP_RUN 3  /* the whole run of step launches of a forward
                                  or adjoint time loop (wf_profile_runs_enable) */
+#define WF_KERNEL_STEP2   4   /* the two-update kernel (wf_two_step_enable)    */
+#define WF_KERNEL_STEP2_RUN 5 /* the run of two-update launches of a forward
+                                 time loop (wf_profile_runs_enable)           */
 
-/* While enabled (process-wide), launches of the three kernels above are
+/* While enabled (process-wide), launches of the kernels WF_KERNEL_STEP,
+ * WF_KERNEL_INJECT, WF_KERNEL_SAMPLE and WF_KERNEL_STEP2 are
  * bracketed by a pair of HIP events recorded on the stream they run on:
  * every launch for on == 1, every on-th launch of each kind for on > 1 (a
  * lighter touch on the timed work), none for on == 0. */
@@ -350,7 +373,10 @@ wf_status wf_profile_enable(int on);
  * launch count is the number of step launches those spans cover, so that the
  * summed time over the count is the average duration of one step launch
  * (gaps between the back-to-back launches included) with two events per
- * loop. Like per-launch timing, it suspends graph capture. */
+ * loop. A forward loop that runs two updates per launch records its run of
+ * two-update launches as kind WF_KERNEL_STEP2_RUN the same way (and any
+ * single update left over as WF_KERNEL_STEP_RUN). Like per-launch timing, it
+ * suspends graph capture. */
 wf_status wf_profile_runs_enable(int on);
 
 /* Synchronise on the recorded events and return, for kernel `kind`, the summed
@@ -361,7 +387,9 @@ wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int res
 /* Number of step-kernel launches made since the last reset in kernel mode
  * `mode`: 0 the plain update (forward and adjoint steps, the gradient's
  * forward and recomputed steps), 1 the update with imaging (the gradient's
- * reverse steps), 2 the Born background step, 3 the Born scattered step.
+ * reverse steps), 2 the Born background step, 3 the Born scattered step, 4
+ * the two-update launches of forward loops (each advancing two plain
+ * updates).
  * Counted on the host for every launch, whether timing is on or not; reset
  * != 0 clears every mode after reading. Batched launches of the serving
  * engine are not counted. */

@@ -101,6 +101,7 @@ def _load():
         "wf_model_graph_launches": (I64, [P]),
         "wf_model_trim": (I, [P]),
         "wf_graph_enable": (I, [I]),
+        "wf_two_step_enable": (I, [I]),
         "wf_model_destroy": (I, [P]),
         "wf_forward": (I, [P, D, I, I, P, P, I, P, P, P, I, P]),
         "wf_forward_noalloc": (I, [P, D, I, I, P, P, I, P, P, P]),
@@ -139,6 +140,7 @@ lib = _load()
 # every symbol declared in include/wavefd.h
 EXPORTS = ("wf_last_error", "wf_version", "wf_critical_dt", "wf_geom_shape", "wf_model_create",
            "wf_model_set_m", "wf_model_bytes", "wf_model_graph_launches", "wf_graph_enable",
+           "wf_two_step_enable",
            "wf_model_trim",
            "wf_model_destroy", "wf_forward", "wf_forward_noalloc", "wf_adjoint",
            "wf_gradient", "wf_born", "wf_fwi_gradient", "wf_model_update", "wf_revolve_forward_steps", "wf_revolve_schedule",
@@ -252,6 +254,12 @@ def wf_graph_enable(on: bool):
     _check(lib.wf_graph_enable(1 if on else 0))
 
 
+def wf_two_step_enable(mode: int):
+    """Two updates per launch in 3D forward loops: 0 off, 1 where measured
+    faster (the default), 2 for every compiled order (4 and 8)."""
+    _check(lib.wf_two_step_enable(int(mode)))
+
+
 def wf_model_destroy(model):
     _check(lib.wf_model_destroy(model))
 
@@ -351,6 +359,9 @@ WF_KERNEL_STEP = 0
 WF_KERNEL_INJECT = 1
 WF_KERNEL_SAMPLE = 2
 WF_KERNEL_STEP_RUN = 3
+WF_KERNEL_STEP2 = 4
+WF_KERNEL_STEP2_RUN = 5
+WF_STEP_LAUNCHES_TWO = 4   # wf_profile_step_launches: two-update launches
 
 
 def wf_profile_enable(on):

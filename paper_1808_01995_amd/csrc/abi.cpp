@@ -101,6 +101,8 @@ wf_status wf_model_trim(wf_model* model) {
     if (st != WF_OK) return st;
     md.ws.reset();
     md.ws_clean = false;
+    md.d_u2[0].reset();
+    md.d_u2[1].reset();
     return WF_OK;
     ABI_GUARD_END
 }
@@ -119,6 +121,12 @@ wf_status wf_validate_enable(int on) {
 
 wf_status wf_graph_enable(int on) {
     set_graphs_enabled(on != 0);
+    return WF_OK;
+}
+
+wf_status wf_two_step_enable(int mode) {
+    if (mode < 0 || mode > 2) return fail(WF_E_ARG, "two-step mode must be 0, 1 or 2");
+    set_two_step_mode(mode);
     return WF_OK;
 }
 

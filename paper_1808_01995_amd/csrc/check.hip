@@ -31,6 +31,8 @@ wf_status count_ghost_nonzero(const Model& md, int64_t* out) {
     *out = 0;
     const Layout& L = md.L;
     std::vector<const float*> allocs = {md.d_kap.f(), md.d_u[0].f(), md.d_u[1].f()};
+    for (const DevBuf& b : md.d_u2)
+        if (b.ptr) allocs.push_back(b.f());
     // every field slot of the gradient workspace while it is marked clean
     if (md.ws_clean && md.ws.ptr) {
         const int64_t stride = (L.alloc_elems + 63) / 64 * 64;

@@ -145,6 +145,64 @@ struct TeamArgs {
 bool team_fits(int64_t nx, int64_t ny, int64_t nz);
 hipError_t launch_team(const TeamArgs& a, int ndim, int half, int nwg, hipStream_t s);
 
+// Two plain updates in one pass (3D, half orders 2 and 4): u^{n+1} and
+// u^{n+2} from u^n and u^{n-1}, each node with the arithmetic of the
+// single-update kernel (so the fields are the same bits). A block owns an
+// inner (y, z) tile of by x 4(kStep2Cols - 2 hz) nodes (hz = ceil(M / 4)) and
+// an x chunk; it computes u^{n+1} on the tile extended by M rows and 4 hz
+// nodes on each side and on M planes beyond either end of its chunk, keeps it
+// in registers and LDS, and from it u^{n+2} on the inner tile. Reads u^n,
+// u^{n-1} and kap, writes u^{n+1} and u^{n+2} (20 bytes per node for two
+// updates). None of the four fields may alias another: neighbouring blocks
+// read cur and old where this block writes.
+constexpr int kStep2Cols = 32;    // float4 columns per row of the extended tile
+constexpr int kInjCap2x = 512;    // injection entries per block and update
+struct Step2Params {
+    const float* cur;    // u^n
+    const float* old;    // u^{n-1}
+    float* out1;         // u^{n+1}
+    float* out2;         // u^{n+2}
+    const float* kap;
+    const float* etax;
+    const float* etay;
+    const float* etaz;
+    int nx, ny, nz;
+    int64_t sx, sy;
+    int cx;              // x-chunk length per block
+    int ntz, nty, nchunks, nblocks;
+    int by;              // host side: the compiled tile height the planner chose
+    float c0;
+    float wx[kMaxHalf + 1], wy[kMaxHalf + 1], wz[kMaxHalf + 1];
+    float inv2dt;
+    // receivers: block r samples points [r smp_per, (r + 1) smp_per) of cur
+    // into smp_cur and of old into smp_old (either may be NULL)
+    const int64_t* smp_off;
+    const float* smp_w;
+    float* smp_cur;
+    float* smp_old;
+    int smp_n, smp_per;
+    // injection, as in StepParams, for the first update ([0]: entries over
+    // the extended tile and chunk, increments of step n) and the second ([1]:
+    // the inner tile and chunk, step n + 1); inj_blk[k] NULL: none
+    const int* inj_blk[2];
+    const int2* inj_thr[2];
+    const int* inj_x[2];
+    const float4* inj_inc[2];
+};
+// Whether the two-update kernel is compiled for (ndim, half), and whether
+// it was measured faster than two single-update launches on a grid of that
+// many nodes.
+bool step2_supported(int ndim, int half);
+bool step2_preferred(int ndim, int half, int64_t nodes);
+// Plan tiles and chunks from the grid in p (nx, ny, nz set); cx_request > 0
+// forces the chunk length.
+void step2_plan(Step2Params& p, int half, int cx_request);
+// Threads per block of the planned launch, and the extension in rows and
+// float4 columns on each side of the inner tile.
+int step2_threads(int half, int by);
+int step2_ext_cols(int half);
+hipError_t launch_step2(const Step2Params& p, int half, hipStream_t s);
+
 // Tile shapes (threads along z carry 4 points each).
 struct TileShape {
     int bz, by;   // threads along z and y per block

@@ -482,6 +482,349 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 }
 
 // ---------------------------------------------------------------------------
+// Two plain updates per pass (3D): temporal blocking over overlapping tiles.
+//
+// Block: EY = BY + 2M rows of kStep2Cols threads, one float4 column each,
+// over the extended tile; the inner tile is rows [M, M + BY) and columns
+// [HZ, kStep2Cols - HZ). For its chunk [xb, xe) the block walks planes
+// x = xb - M .. xe + M - 1: every thread forms u^{n+1}(x) of its column from
+// a register ring of u^n planes (x taps) and an LDS plane of u^n that holds
+// the extended tile plus a frame of M rows and P nodes (y and z taps), and
+// keeps it in a register ring of u^{n+1} planes; the inner threads then form
+// u^{n+2}(x - M) from that ring and an LDS plane of u^{n+1}(x - M), whose y
+// and z neighbours the extended tile holds. u^{n+1} is zero outside the grid
+// (columns outside it, planes outside [0, nx)), as the fields of the
+// single-update loop are. Every node gets the arithmetic of step_body in the
+// same order, so both fields equal two single updates bit for bit. Both LDS
+// planes alternate between two buffers: one barrier per plane.
+// ---------------------------------------------------------------------------
+// PF: planes the u^n ring prefetches; LA: planes of lookahead of u^{n-1} and
+// kap; KR: the second update reloads kap (else a register ring keeps M + 1
+// planes of it, LA = 1 only); NT: u^{n-1} and kap streamed non-temporal
+// (else cached, so that the overlapping rows of neighbouring blocks can hit).
+template <int M, int BY, int PF, int LA, bool KR, bool NTS>
+__device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx) {
+    constexpr int HZ = (M + 3) / 4;
+    constexpr int P = 4 * HZ;              // z extension and z frame (nodes)
+    constexpr int BZE = kStep2Cols;
+    constexpr int TZ = 4 * (BZE - 2 * HZ); // inner tile along z
+    constexpr int EY = BY + 2 * M;         // rows of the extended tile
+    constexpr int NT = EY * BZE;
+    constexpr int LWA = 4 * BZE + 2 * P;   // u^n plane: row width with the z frame
+    constexpr int LBA = (EY + 2 * M) * LWA;
+    constexpr int LWU = 4 * BZE;           // u^{n+1} plane: the extended tile
+    constexpr int LBU = EY * LWU;
+    constexpr int NQ = 2 * M + 1 + PF;     // u^n ring; the u^{n+1} ring has the same length
+    constexpr int KQ = KR ? 1 : M + 1;     // kap of planes x - M .. x
+    constexpr int HL = 2;                  // planes of lookahead of the frame loads
+    static_assert(NQ % KQ == 0 && NQ % HL == 0 && NQ % LA == 0, "ring lengths must divide the unrolled loop");
+    static_assert(KR || LA == 1, "the kap ring takes the next plane only");
+    auto lds_ = [](const float* q) { return NTS ? ld4s(q) : ld4(q); };
+    constexpr int NFY = 2 * M * BZE;       // frame rows above and below (float4 loads)
+    constexpr int NFZ = 2 * EY * HZ;       // frame columns left and right
+    constexpr int JF = (NFY + NFZ + NT - 1) / NT;
+    __shared__ __attribute__((aligned(16))) float la[2 * LBA];
+    __shared__ __attribute__((aligned(16))) float lu[2 * LBU];
+    __shared__ int inj_xl[2][kInjCap2x];
+    __shared__ float4 inj_vl[2][kInjCap2x];
+
+    const int r = xcd_remap(bidx, p.nblocks);
+    if (r >= p.nblocks) return;
+    int t = r;
+    const int itz = t % p.ntz;
+    t /= p.ntz;
+    const int ity = t % p.nty;
+    const int ich = t / p.nty;
+
+    const int tid = threadIdx.x;
+    const int lz = tid % BZE, ly = tid / BZE;
+    const int z0 = itz * TZ, y0 = ity * BY;
+    const int y = y0 - M + ly, z = z0 - P + 4 * lz;
+    const bool ing = y >= 0 && y < p.ny && z >= 0 && z < p.nz;
+    const bool inner = ly >= M && ly < M + BY && lz >= HZ && lz < BZE - HZ;
+    const int xb = ich * p.cx;
+    const int xe = min(xb + p.cx, p.nx);
+    const int xs = xb - M, xend = xe + M;
+    const int64_t sx = p.sx;
+    // as in step_body: unconditional loads, column 0 for threads outside the grid
+    const int64_t col = ing ? (int64_t)y * p.sy + z : 0;
+
+    int hf_l[JF];
+    int64_t hf_c[JF];
+    bool hf_v[JF];
+#pragma unroll
+    for (int j = 0; j < JF; ++j) {
+        const int i = tid + j * NT;
+        hf_l[j] = -1;
+        hf_v[j] = false;
+        hf_c[j] = 0;
+        int gy = -1, gz = -1, l = -1;
+        if (i < NFY) {
+            const int rr = i / BZE, cz = i - rr * BZE;
+            const int lr = rr < M ? rr : rr + EY;
+            gy = y0 - 2 * M + lr;
+            gz = z0 - P + 4 * cz;
+            l = lr * LWA + P + 4 * cz;
+        } else if (i < NFY + NFZ) {
+            const int k = i - NFY;
+            const int rr = k / (2 * HZ), kk = k - rr * (2 * HZ);
+            const int side = kk / HZ, q = kk - side * HZ;
+            const int lc = side ? (P + 4 * BZE + 4 * q) : 4 * q;
+            gy = y0 - M + rr;
+            gz = z0 - 2 * P + lc;
+            l = (rr + M) * LWA + lc;
+        }
+        if (l >= 0) {
+            hf_l[j] = l;
+            hf_v[j] = gy >= 0 && gy < p.ny && gz >= 0 && gz < p.nz;
+            hf_c[j] = hf_v[j] ? (int64_t)gy * p.sy + gz : 0;
+        }
+    }
+
+    float eyz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        eyz[i] = (ing && z + i < p.nz) ? (p.etay[y] + p.etaz[z + i]) : 0.0f;
+
+    // injection entries of both updates -> LDS; each thread's next entry of
+    // each list in registers (as in step_body)
+    int inj_i[2] = {0, 0}, inj_e[2] = {0, 0}, inj_nx[2] = {INT_MAX, INT_MAX};
+    float4 inj_nv[2] = {zero4(), zero4()};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (!p.inj_blk[k]) continue;
+        const int b0 = p.inj_blk[k][r], b1 = p.inj_blk[k][r + 1];
+        if (b1 <= b0) continue;
+        for (int i = tid; i < b1 - b0; i += NT) {
+            inj_xl[k][i] = p.inj_x[k][b0 + i];
+            inj_vl[k][i] = p.inj_inc[k][b0 + i];
+        }
+        const int2 rg = p.inj_thr[k][(int64_t)r * NT + tid];
+        inj_i[k] = rg.x - b0;
+        inj_e[k] = rg.y - b0;
+        if (inj_i[k] < inj_e[k]) {
+            inj_nx[k] = p.inj_x[k][rg.x];
+            inj_nv[k] = p.inj_inc[k][rg.x];
+        }
+    }
+
+    float4 ring[NQ], uring[NQ], kring[KQ], uo_q[LA], kp_q[LA];
+#pragma unroll
+    for (int s = 0; s < 2 * M + PF; ++s) ring[s] = ld4(p.cur + (int64_t)(xs - M + s) * sx + col);
+    ring[NQ - 1] = zero4();
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) uring[s] = zero4();
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) kring[s] = zero4();
+#pragma unroll
+    for (int s = 0; s < LA; ++s) {
+        uo_q[s] = lds_(p.old + (int64_t)(xs + s) * sx + col);
+        kp_q[s] = KR ? lds_(p.kap + (int64_t)(xs + s) * sx + col) : zero4();
+    }
+    if (!KR) kring[0] = lds_(p.kap + (int64_t)xs * sx + col);
+    float4 hq[HL][JF];
+    auto load_frame = [&](int sl, int xx) {
+        const int64_t b = (int64_t)xx * sx;
+#pragma unroll
+        for (int j = 0; j < JF; ++j) hq[sl][j] = ld4(p.cur + b + hf_c[j]);
+    };
+#pragma unroll
+    for (int i = 0; i < HL; ++i) load_frame(i, xs + i);
+
+    // this block's share of the receivers, from both fields it only reads
+    // (k_sample's corner order)
+    if (p.smp_cur || p.smp_old) {
+        constexpr int KS = 8;
+        const int s0 = r * p.smp_per, s1 = min(s0 + p.smp_per, p.smp_n);
+        for (int i = s0 + tid; i < s1; i += NT) {
+            int64_t so[KS];
+            float sw[KS];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                so[k] = p.smp_off[(int64_t)i * KS + k];
+                sw[k] = p.smp_w[(int64_t)i * KS + k];
+            }
+            if (p.smp_cur) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) acc = fmaf(sw[k], p.cur[so[k]], acc);
+                p.smp_cur[i] = acc;
+            }
+            if (p.smp_old) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) acc = fmaf(sw[k], p.old[so[k]], acc);
+                p.smp_old[i] = acc;
+            }
+        }
+    }
+
+    for (int xg = xs; xg < xend; xg += NQ) {
+#pragma unroll
+        for (int ph = 0; ph < NQ; ++ph) {
+            const int x = xg + ph;
+            if (x < xend) {   // uniform
+                const float4 uo = uo_q[ph % LA];
+                const float4 kp = KR ? kp_q[ph % LA] : kring[ph % KQ];
+                float4 hf[JF];
+#pragma unroll
+                for (int j = 0; j < JF; ++j) hf[j] = hq[ph % HL][j];
+                load_frame(ph % HL, x + HL);   // planes beyond the grid are ghost planes
+                uo_q[ph % LA] = lds_(p.old + (int64_t)(x + LA) * sx + col);
+                float4 kpn = zero4(), kp2r = zero4();
+                if (KR) {
+                    kp_q[ph % LA] = lds_(p.kap + (int64_t)(x + LA) * sx + col);
+                    kp2r = ld4(p.kap + (int64_t)(x - M) * sx + col);   // for the second update
+                } else {
+                    kpn = lds_(p.kap + (int64_t)(x + 1) * sx + col);
+                }
+                ring[(ph + 2 * M + PF) % NQ] = ld4(p.cur + (int64_t)(x + M + PF) * sx + col);
+                const float4 c = ring[(ph + M) % NQ];
+                float* A = la + (x & 1) * LBA;
+                float* U = lu + (x & 1) * LBU;
+                float* arow = A + (ly + M) * LWA;
+                float* urow = U + ly * LWU;
+                st4(arow + P + 4 * lz, ing ? c : zero4());
+#pragma unroll
+                for (int j = 0; j < JF; ++j)
+                    if (hf_l[j] >= 0) st4(A + hf_l[j], hf_v[j] ? hf[j] : zero4());
+                st4(urow + 4 * lz, uring[(ph + NQ - M) % NQ]);   // u^{n+1}(x - M)
+                __syncthreads();
+
+                // first update: u^{n+1}(x) on the extended tile
+                {
+                    float lap[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) lap[i] = p.c0 * comp(c, i);
+#pragma unroll
+                    for (int j = 1; j <= M; ++j) {
+                        const float4 a = ring[(ph + M - j) % NQ], b = ring[(ph + M + j) % NQ];
+                        lap[0] = fmaf(p.wx[j], a.x + b.x, lap[0]);
+                        lap[1] = fmaf(p.wx[j], a.y + b.y, lap[1]);
+                        lap[2] = fmaf(p.wx[j], a.z + b.z, lap[2]);
+                        lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
+                    }
+#pragma unroll
+                    for (int j = 1; j <= M; ++j) {
+                        const float4 a = ld4(arow - j * LWA + P + 4 * lz);
+                        const float4 b = ld4(arow + j * LWA + P + 4 * lz);
+                        lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
+                        lap[1] = fmaf(p.wy[j], a.y + b.y, lap[1]);
+                        lap[2] = fmaf(p.wy[j], a.z + b.z, lap[2]);
+                        lap[3] = fmaf(p.wy[j], a.w + b.w, lap[3]);
+                    }
+                    {
+                        float w[2 * P + 4];
+#pragma unroll
+                        for (int k = 0; k < (2 * P + 4) / 4; ++k) {
+                            const float4 v = ld4(arow + 4 * lz + 4 * k);
+                            w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int j = 1; j <= M; ++j)
+                                lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+                    }
+                    const float ex = p.etax[min(max(x, 0), p.nx - 1)];
+                    float4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float v = update(comp(c, i), comp(uo, i), comp(kp, i), lap[i], ex + eyz[i], p.inv2dt);
+                        if (z + i >= p.nz) v = 0.0f;
+                        set_comp(o, i, v);
+                    }
+                    if (inj_nx[0] == x) {
+                        const float4 inc = inj_nv[0];
+                        o.x += inc.x; o.y += inc.y; o.z += inc.z; o.w += inc.w;
+                        ++inj_i[0];
+                        if (inj_i[0] < inj_e[0]) {
+                            inj_nx[0] = inj_xl[0][inj_i[0]];
+                            inj_nv[0] = inj_vl[0][inj_i[0]];
+                        } else {
+                            inj_nx[0] = INT_MAX;
+                        }
+                    }
+                    if (!ing || x < 0 || x >= p.nx) o = zero4();
+                    uring[ph % NQ] = o;
+                }
+
+                // second update: u^{n+2}(x - M) on the inner tile
+                if (x >= xb + M && inner) {   // uniform in x; the z edge columns diverge
+                    const int x2 = x - M;
+                    const float4 c2 = uring[(ph + NQ - M) % NQ];
+                    float lap[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) lap[i] = p.c0 * comp(c2, i);
+#pragma unroll
+                    for (int j = 1; j <= M; ++j) {
+                        const float4 a = uring[(ph + NQ - M - j) % NQ], b = uring[(ph + NQ - M + j) % NQ];
+                        lap[0] = fmaf(p.wx[j], a.x + b.x, lap[0]);
+                        lap[1] = fmaf(p.wx[j], a.y + b.y, lap[1]);
+                        lap[2] = fmaf(p.wx[j], a.z + b.z, lap[2]);
+                        lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
+                    }
+#pragma unroll
+                    for (int j = 1; j <= M; ++j) {
+                        const float4 a = ld4(urow - j * LWU + 4 * lz);
+                        const float4 b = ld4(urow + j * LWU + 4 * lz);
+                        lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
+                        lap[1] = fmaf(p.wy[j], a.y + b.y, lap[1]);
+                        lap[2] = fmaf(p.wy[j], a.z + b.z, lap[2]);
+                        lap[3] = fmaf(p.wy[j], a.w + b.w, lap[3]);
+                    }
+                    {
+                        float w[2 * P + 4];
+#pragma unroll
+                        for (int k = 0; k < (2 * P + 4) / 4; ++k) {
+                            const float4 v = ld4(urow + 4 * lz - P + 4 * k);
+                            w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int j = 1; j <= M; ++j)
+                                lap[i] = fmaf(p.wz[j], w[P + i - j] + w[P + i + j], lap[i]);
+                    }
+                    const float4 uo2 = ring[ph % NQ];          // u^n(x - M)
+                    const float4 kp2 = KR ? kp2r : kring[(ph + 1) % KQ];   // kap(x - M)
+                    const float ex = p.etax[x2];
+                    float4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float v = update(comp(c2, i), comp(uo2, i), comp(kp2, i), lap[i], ex + eyz[i], p.inv2dt);
+                        if (z + i >= p.nz) v = 0.0f;
+                        set_comp(o, i, v);
+                    }
+                    if (inj_nx[1] == x2) {
+                        const float4 inc = inj_nv[1];
+                        o.x += inc.x; o.y += inc.y; o.z += inc.z; o.w += inc.w;
+                        ++inj_i[1];
+                        if (inj_i[1] < inj_e[1]) {
+                            inj_nx[1] = inj_xl[1][inj_i[1]];
+                            inj_nv[1] = inj_vl[1][inj_i[1]];
+                        } else {
+                            inj_nx[1] = INT_MAX;
+                        }
+                    }
+                    if (ing) {
+                        const int64_t base = (int64_t)x2 * sx;
+                        st4o(p.out1 + base + col, c2);
+                        st4o(p.out2 + base + col, o);
+                    }
+                }
+                if (!KR) kring[(ph + 1) % KQ] = kpn;   // kap(x + 1), in the slot of kap(x - M)
+            }
+        }
+    }
+}
+
+template <int M, int BY, int PF, int LA, bool KR, bool NTS>
+__global__ void __launch_bounds__((BY + 2 * M) * kStep2Cols, 1) k_step2(const Step2Params p) {
+    step2_body<M, BY, PF, LA, KR, NTS>(p, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // resident teams: one work-group steps one small grid held in LDS
 // ---------------------------------------------------------------------------
 // Dense LDS layout [x][y][zp], zp = z padded to 4 (the pad holds zeros).
@@ -853,10 +1196,6 @@ __device__ inline bool team_fits_dev(int nx, int ny, int nz) {
     return nx > 0 && ny > 0 && nz > 0 && (int64_t)nx * ny * ((nz + 3) / 4 * 4) * 2 <= kTeamFieldFloats;
 }
 
-// A launch of resident teams: work-groups take the launch's shots in order
-// (one counter in device memory, zero at the launch), each stepping its shot
-// to the end in LDS before it takes the next. The job is read from the table
-// with a uniform index, so its scalars live in scalar registers.
 // A launch of resident teams. Width 1: work-groups take the launch's shots in
 // order (one counter in device memory, zero at the launch), each stepping its
 // shot to the end in LDS before it takes the next. Width W > 1: work-groups
@@ -1231,6 +1570,101 @@ hipError_t launch_step(const StepParams& p, int ndim, int half, int mode, hipStr
     const int grid = ((p.nblocks + 7) / 8) * 8;
     void* args[] = {const_cast<StepParams*>(&p)};
     return hipLaunchKernel(fn, dim3(grid), dim3(ts.bz * ts.by), args, 0, s);
+}
+
+// Two-update kernel: 16 inner rows (20 or 24 extended rows of 32 float4
+// columns: 640 or 768 threads), one block per CU (its two rings and the LDS
+// reads in flight hold about 160 VGPRs); the u^n ring prefetches one plane.
+// Per order, as measured at 592^3 (us per launch of two updates): order 4
+// with u^{n-1} and kap cached (neighbouring blocks re-read the rows their
+// extended tiles share: 1129 against 1195 streamed), order 8 also reloading
+// kap for the second update instead of keeping a ring of it (1424 against
+// 1525: the ring spilled); a deeper prefetch spilled more and was slower.
+constexpr int kStep2By = 16;
+// Measured against two single-update launches (us per update, constant
+// velocity, 40 updates): order 4 gains 1.13-1.16 x from 464^3 (1.0e8 nodes)
+// to 592^3, breaks even at 400^3 and loses at 272^3 and 336^3 (0.90-0.94 x),
+// where the single-update kernel finds much of its traffic in the Infinity
+// Cache; order 8 is bound by instruction issue (every tile recomputes u^{n+1}
+// on a margin of M rows and 4 nodes) and loses at every size from 208^3 to
+// 592^3 (0.76-0.93 x).
+constexpr int64_t kStep2MinNodes = 80000000;
+
+namespace {
+const void* step2_fn(int half) {
+    switch (half) {
+        case 2: return reinterpret_cast<const void*>(&k_step2<2, kStep2By, 1, 1, false, false>);
+        case 4: return reinterpret_cast<const void*>(&k_step2<4, kStep2By, 1, 1, true, false>);
+        default: return nullptr;
+    }
+}
+}  // namespace
+
+bool step2_supported(int ndim, int half) { return ndim == 3 && step2_fn(half) != nullptr; }
+bool step2_preferred(int ndim, int half, int64_t nodes) {
+    return step2_supported(ndim, half) && half == 2 && nodes >= kStep2MinNodes;
+}
+int step2_ext_cols(int half) { return (half + 3) / 4; }
+int step2_threads(int half, int by) { return (by + 2 * half) * kStep2Cols; }
+
+void step2_plan(Step2Params& p, int half, int cx_request) {
+    static std::mutex mu;
+    static int cap_cache[kMaxHalf + 1] = {};
+    p.by = kStep2By;
+    const int tz = 4 * (kStep2Cols - 2 * step2_ext_cols(half));
+    p.ntz = (p.nz + tz - 1) / tz;
+    p.nty = (p.ny + p.by - 1) / p.by;
+    const int64_t tiles = (int64_t)p.ntz * p.nty;
+    int cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cap_cache[half] <= 0) {
+            int dev = 0, cus = 0, per = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                cus = 256;
+            const void* fn = step2_fn(half);
+            if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, step2_threads(half, p.by), 0) !=
+                           hipSuccess || per < 1)
+                per = 1;
+            cap_cache[half] = per * cus;
+        }
+        cap = cap_cache[half];
+    }
+    int cx = cx_request;
+    if (cx <= 0) {
+        // as step_plan: every chunk walks 2M planes beyond its own (the
+        // first update's extension), rounds beyond the first cost kRoundPlanes
+        constexpr double kRoundPlanes = 8.0;
+        const int warm = 2 * half;
+        double best = 1e300;
+        int best_n = 1;
+        for (int n = 1; n <= p.nx; ++n) {
+            const int c = (p.nx + n - 1) / n;
+            if (n > 1 && (p.nx + c - 1) / c != n) continue;
+            const double blocks = (double)tiles * n;
+            const double rounds = std::ceil(blocks / cap);
+            const double fill = std::min(1.0, blocks / cap);
+            const double cost = rounds * (c + warm) / fill + (rounds - 1) * kRoundPlanes;
+            if (cost < best * 0.999) {
+                best = cost;
+                best_n = n;
+            }
+        }
+        cx = (p.nx + best_n - 1) / best_n;
+    }
+    p.cx = std::max(1, std::min(cx, p.nx));
+    p.nchunks = (p.nx + p.cx - 1) / p.cx;
+    p.nblocks = (int)(tiles * p.nchunks);
+}
+
+hipError_t launch_step2(const Step2Params& p, int half, hipStream_t s) {
+    if (p.nblocks <= 0) return hipSuccess;
+    const void* fn = step2_fn(half);
+    if (!fn || p.by != kStep2By) return hipErrorInvalidValue;
+    const int grid = ((p.nblocks + 7) / 8) * 8;
+    void* args[] = {const_cast<Step2Params*>(&p)};
+    return hipLaunchKernel(fn, dim3(grid), dim3(step2_threads(half, p.by)), args, 0, s);
 }
 
 template <int M>

@@ -10,7 +10,8 @@ namespace wf {
 
 namespace {
 
-constexpr int kKinds = 4;         // WF_KERNEL_STEP .. WF_KERNEL_STEP_RUN
+constexpr int kKinds = 6;         // WF_KERNEL_STEP .. WF_KERNEL_STEP2_RUN
+constexpr int kCounted = kModeCount + 1;   // step modes, then two-update launches
 
 struct Rec {
     int kind;
@@ -21,12 +22,12 @@ struct Rec {
 std::mutex g_mu;
 int g_on = 0;                     // sampling stride, 0 = off
 bool g_runs = false;              // whole runs of step launches timed as one span
-int64_t g_seen[3] = {0, 0, 0};    // launches seen per kind while enabled
+int64_t g_seen[kKinds] = {};      // launches seen per kind while enabled
 std::vector<Rec> g_recs;          // recorded, not yet read
 std::vector<hipEvent_t> g_free;   // reusable events
-double g_ms[kKinds] = {0, 0, 0, 0};
-int64_t g_n[kKinds] = {0, 0, 0, 0};
-std::atomic<int64_t> g_launches[kModeCount];   // step launches per mode (always counted)
+double g_ms[kKinds] = {};
+int64_t g_n[kKinds] = {};
+std::atomic<int64_t> g_launches[kCounted];   // step launches per mode (always counted)
 
 hipEvent_t get_event() {
     if (!g_free.empty()) {
@@ -73,10 +74,10 @@ bool profiling_active() {
 }
 
 void count_step_launch(int mode) {
-    if (mode >= 0 && mode < kModeCount) g_launches[mode].fetch_add(1, std::memory_order_relaxed);
+    if (mode >= 0 && mode < kCounted) g_launches[mode].fetch_add(1, std::memory_order_relaxed);
 }
 
-RunSpan::RunSpan(hipStream_t st) : s(st) {
+RunSpan::RunSpan(hipStream_t st, int k) : s(st), kind(k) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_runs) return;
     if (g_recs.size() > 4096) drain(false);
@@ -93,7 +94,7 @@ void RunSpan::finish(int64_t launches) {
     if (!a) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (launches > 0 && hipEventRecord(b, s) == hipSuccess) {
-        g_recs.push_back({WF_KERNEL_STEP_RUN, a, b, launches});
+        g_recs.push_back({kind, a, b, launches});
     } else {
         g_free.push_back(a);
         g_free.push_back(b);
@@ -110,7 +111,7 @@ RunSpan::~RunSpan() {
 
 ProfScope::ProfScope(int k, hipStream_t st) : kind(k), s(st) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_on <= 0 || k < 0 || k > 2) return;
+    if (g_on <= 0 || k < 0 || k >= kKinds || k == WF_KERNEL_STEP_RUN || k == WF_KERNEL_STEP2_RUN) return;
     if (g_seen[k]++ % g_on != 0) return;
     if (g_recs.size() > 4096) drain(false);
     a = get_event();
@@ -143,7 +144,7 @@ wf_status wf_profile_enable(int on) {
     if (on < 0) return fail(WF_E_ARG, "negative profiling stride");
     std::lock_guard<std::mutex> lk(g_mu);
     g_on = on;
-    for (int k = 0; k < 3; ++k) g_seen[k] = 0;
+    for (int k = 0; k < kKinds; ++k) g_seen[k] = 0;
     return WF_OK;
 }
 
@@ -154,10 +155,10 @@ wf_status wf_profile_runs_enable(int on) {
 }
 
 wf_status wf_profile_step_launches(int mode, int64_t* count, int reset) {
-    if (mode < 0 || mode >= kModeCount) return fail(WF_E_ARG, "unknown step mode %d", mode);
+    if (mode < 0 || mode >= kCounted) return fail(WF_E_ARG, "unknown step mode %d", mode);
     if (count) *count = g_launches[mode].load();
     if (reset)
-        for (int k = 0; k < kModeCount; ++k) g_launches[k].store(0);
+        for (int k = 0; k < kCounted; ++k) g_launches[k].store(0);
     return WF_OK;
 }
 

@@ -114,14 +114,18 @@ struct Injector {
 
     IncParams ip{};
     // host side: tables and buffers (synchronous work, never captured)
+    // geom: the thread layout of another kernel than p's single-update launch
     wf_status plan(Model& md, const PointSet& set, const StepParams& p, const float* series,
-                   int nrows, DevBuf& buf, hipStream_t s) {
+                   int nrows, DevBuf& buf, hipStream_t s, const InjGeom* geom = nullptr) {
         ps = &set;
         vals = series;
         fz = nullptr;
         if (set.nnodes == 0) return WF_OK;
         if (!fused_injection_disabled()) {
-            WF_TRY(set.fused(md.L, p, &fz));
+            if (geom)
+                WF_TRY(set.fused(md.L, *geom, &fz));
+            else
+                WF_TRY(set.fused(md.L, p, &fz));
             if (!fz->ok) fz = nullptr;
         }
         if (!fz) return WF_OK;
@@ -283,6 +287,21 @@ wf_status run_maybe_graph(Model& md, const GraphKey& key, hipStream_t s, F&& enq
 
 void set_graphs_enabled(bool on) { graph_switch().store(on ? 1 : 0); }
 
+namespace {
+// 0 off, 1 where the two-update kernel was measured faster, 2 wherever compiled
+std::atomic<int>& two_step_switch() {
+    static std::atomic<int> mode{[] {
+        const char* e = std::getenv("WAVEFD_TWO_STEP");
+        if (e && e[0] == '0') return 0;
+        if (e && e[0] == '2') return 2;
+        return 1;
+    }()};
+    return mode;
+}
+}  // namespace
+
+void set_two_step_mode(int mode) { two_step_switch().store(std::min(2, std::max(0, mode))); }
+
 bool fused_injection_disabled() { return std::getenv("WAVEFD_NO_FUSED_INJECT") != nullptr; }
 
 void set_thread_throttle(int steps) {
@@ -300,11 +319,76 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
     md.fill_step(p, dt, false);
     Injector inj;
     WF_TRY(inj.plan(md, src, p, src_wav, nt, inc_buf ? *inc_buf : md.d_inc[0], s));
+
+    // Two updates per launch (3D, compiled orders) for loops of two updates
+    // or more; calls that allocate from an arena or a fixed scratch keep one.
+    Step2Params p2{};
+    Injector inj2[2];
+    const int two_mode = two_step_switch().load(std::memory_order_relaxed);
+    bool two = nt >= 3 && step2_supported(L.ndim, md.half) &&
+               (two_mode == 2 || (two_mode == 1 && step2_preferred(L.ndim, md.half, L.npoints))) &&
+               !thread_arena_active() && !thread_scratch_active() &&
+               !(src.nnodes > 0 && fused_injection_disabled());
+    if (two) {
+        p2.kap = p.kap;
+        p2.etax = p.etax;
+        p2.etay = p.etay;
+        p2.etaz = p.etaz;
+        p2.nx = p.nx;
+        p2.ny = p.ny;
+        p2.nz = p.nz;
+        p2.sx = p.sx;
+        p2.sy = p.sy;
+        p2.c0 = p.c0;
+        std::copy(p.wx, p.wx + kMaxHalf + 1, p2.wx);
+        std::copy(p.wy, p.wy + kMaxHalf + 1, p2.wy);
+        std::copy(p.wz, p.wz + kMaxHalf + 1, p2.wz);
+        p2.inv2dt = p.inv2dt;
+        step2_plan(p2, md.half, 0);
+        if (src.nnodes > 0) {
+            const int M = md.half, hz = step2_ext_cols(M);
+            InjGeom g;
+            g.tz = 4 * (kStep2Cols - 2 * hz);
+            g.ty = p2.by;
+            g.bz = kStep2Cols;
+            g.nt = step2_threads(M, p2.by);
+            g.ntz = p2.ntz;
+            g.nty = p2.nty;
+            g.cx = p2.cx;
+            g.nchunks = p2.nchunks;
+            g.nblocks = p2.nblocks;
+            g.cap = kInjCap2x;
+            g.tag = 2;
+            InjGeom ge = g;   // first update: the extended tile and chunk
+            ge.ey = M;
+            ge.ez4 = hz;
+            ge.ex = M;
+            InjGeom gi = g;   // second update: the inner tile, numbered in the extended one
+            gi.oy = M;
+            gi.oz4 = hz;
+            WF_TRY(inj2[0].plan(md, src, p, src_wav, nt, md.d_inc[1], s, &ge));
+            WF_TRY(inj2[1].plan(md, src, p, src_wav, nt, md.d_inc[2], s, &gi));
+            two = inj2[0].fz && inj2[1].fz;
+        }
+        if (two) WF_TRY(md.ensure_u2(s));
+    }
+    if (rec.npts > 0) {
+        p2.smp_off = rec.d_off.as<int64_t>();
+        p2.smp_w = rec.d_w.f();
+        p2.smp_n = rec.npts;
+        p2.smp_per = p2.nblocks > 0 ? (int)(((int64_t)rec.npts + p2.nblocks - 1) / p2.nblocks) : 0;
+    }
+
     GraphKey key;
     key.v = {0, (int64_t)nt, bits_of(dt), src.gen, rec.gen, (int64_t)(intptr_t)src_wav,
              (int64_t)(intptr_t)rec_out, (int64_t)(intptr_t)u_save, save_every, p.cx, p.tile,
              (int64_t)(intptr_t)inj.inc, (int64_t)(intptr_t)inj.fz, (int64_t)(intptr_t)md.u(0),
-             (int64_t)(intptr_t)md.u(1), (int64_t)(intptr_t)md.kap()};
+             (int64_t)(intptr_t)md.u(1), (int64_t)(intptr_t)md.kap(), two ? 1 : 0};
+    if (two)
+        for (int64_t v : {(int64_t)p2.cx, (int64_t)(intptr_t)md.u2(0), (int64_t)(intptr_t)md.u2(1),
+                          (int64_t)(intptr_t)inj2[0].inc, (int64_t)(intptr_t)inj2[1].inc,
+                          (int64_t)(intptr_t)inj2[0].fz, (int64_t)(intptr_t)inj2[1].fz})
+            key.v.push_back(v);
     auto enqueue = [&](hipStream_t q) -> wf_status {
         float* A = md.u(0);   // u^n
         float* B = md.u(1);   // u^{n-1}, overwritten by u^{n+1}
@@ -313,9 +397,57 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
         if (u_save) WF_TRY(hip_check(launch_fill(u_save, L.npoints, 0.0f, q), "fill"));
         WF_TRY(inj.enqueue(q));
         if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, q), "fill"));
+        int n = 0;
+        if (two) {
+            // launch at n: u^{n+1} and u^{n+2} from u^n and u^{n-1}; q^n and
+            // q^{n+1} injected; d^n and d^{n-1} sampled from the fields it reads
+            WF_TRY(inj2[0].enqueue(q));
+            WF_TRY(inj2[1].enqueue(q));
+            float* C = md.u2(0);
+            float* D = md.u2(1);
+            Step2Params q2 = p2;
+            RunSpan span2(q, WF_KERNEL_STEP2_RUN);
+            int launches = 0;
+            for (; n + 2 < nt; n += 2) {
+                q2.cur = A;
+                q2.old = B;
+                q2.out1 = C;
+                q2.out2 = D;
+                q2.smp_cur = rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr;
+                q2.smp_old = (rec.npts && n >= 1) ? rec_out + (int64_t)(n - 1) * rec.npts : nullptr;
+                for (int k = 0; k < 2; ++k) {
+                    const Injector& ik = inj2[k];
+                    q2.inj_blk[k] = nullptr;
+                    if (!ik.fz) continue;
+                    q2.inj_blk[k] = ik.fz->blk.as<int>();
+                    q2.inj_thr[k] = ik.fz->thr.as<int2>();
+                    q2.inj_x[k] = ik.fz->x.as<int>();
+                    q2.inj_inc[k] = reinterpret_cast<const float4*>(ik.inc + (int64_t)(n + k) * ik.fz->nnodes);
+                }
+                count_step_launch(kModeCount);
+                {
+                    ProfScope prof(WF_KERNEL_STEP2, q);
+                    WF_TRY(hip_check(launch_step2(q2, md.half, q), "two-update launch"));
+                }
+                WF_TRY(throttle_tick(q));
+                ++launches;
+                if (u_save && (n + 1) % save_every == 0)
+                    WF_TRY(hip_check(launch_unpitch(C, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
+                                                    L.nx, L.ny, L.nz, L.sx, L.sy, q), "save"));
+                if (u_save && (n + 2) % save_every == 0)
+                    WF_TRY(hip_check(launch_unpitch(D, u_save + (int64_t)((n + 2) / save_every) * L.npoints,
+                                                    L.nx, L.ny, L.nz, L.sx, L.sy, q), "save"));
+                std::swap(A, D);   // u^{n+2}
+                std::swap(B, C);   // u^{n+1}
+            }
+            span2.finish(launches);
+            // d^{n-1} is in the old field, which the loop below overwrites
+            if (n >= 1) WF_TRY(sample(rec, B, rec_out + (int64_t)(n - 1) * rec.npts, q));
+        }
         StepParams ps = p;
         RunSpan span(q);
-        for (int n = 0; n + 1 < nt; ++n) {
+        int singles = 0;
+        for (; n + 1 < nt; ++n) {
             // step n: u^{n+1} from u^n, u^{n-1}; q^n injected; d^n = P_r u^n sampled
             inj.configure(ps, n);
             set_sampling(ps, &rec, rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr);
@@ -325,8 +457,9 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
                 WF_TRY(hip_check(launch_unpitch(B, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
                                                 L.nx, L.ny, L.nz, L.sx, L.sy, q), "save"));
             std::swap(A, B);
+            ++singles;
         }
-        span.finish(nt - 1);
+        span.finish(singles);
         if (nt > 1) WF_TRY(sample(rec, A, rec_out + (int64_t)(nt - 1) * rec.npts, q));
         return WF_OK;
     };

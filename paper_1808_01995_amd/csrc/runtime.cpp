@@ -130,6 +130,7 @@ static thread_local PinnedStaging* t_staging = nullptr;
 void set_thread_scratch(ScratchRegion* r) { t_scratch = r; }
 void set_thread_staging(PinnedStaging* p) { t_staging = p; }
 bool thread_scratch_active() { return t_scratch != nullptr; }
+bool thread_arena_active() { return t_arena != nullptr; }
 void set_thread_arena(Arena* a, hipStream_t s) {
     t_arena = a;
     t_arena_stream = a ? s : nullptr;
@@ -387,30 +388,63 @@ PointSet::~PointSet() {
 }
 
 wf_status PointSet::fused(const Layout& L, const StepParams& p, const FusedInj** out) const {
-    *out = nullptr;
     const TileShape ts = step_tile(L.ndim, p.tile);
-    const int NT = ts.bz * ts.by, TZ = 4 * ts.bz, TY = ts.by;
-    const int64_t key[6] = {p.tile, p.ntz, p.nty, p.cx, p.nchunks, NT};
+    InjGeom g;
+    g.tz = 4 * ts.bz;
+    g.ty = ts.by;
+    g.bz = ts.bz;
+    g.nt = ts.bz * ts.by;
+    g.ntz = p.ntz;
+    g.nty = p.nty;
+    g.cx = p.cx;
+    g.nchunks = p.nchunks;
+    g.nblocks = p.nblocks;
+    g.cap = inj_cap(L.ndim);
+    g.tag = p.tile;
+    return fused(L, g, out);
+}
+
+wf_status PointSet::fused(const Layout& L, const InjGeom& g, const FusedInj** out) const {
+    *out = nullptr;
+    const int64_t key[16] = {g.tz, g.ty, g.bz, g.nt, g.ey, g.ez4, g.ex, g.oy, g.oz4, g.ntz, g.nty, g.cx,
+                             g.nchunks, g.nblocks, g.cap, g.tag};
     for (FusedInj* f : fused_cache)
-        if (std::equal(key, key + 6, f->key)) {
+        if (std::equal(key, key + 16, f->key)) {
             *out = f;
             return WF_OK;
         }
     FusedInj* f = new (std::nothrow) FusedInj();
     if (!f) return fail(WF_E_NOMEM, "host allocation");
-    std::copy(key, key + 6, f->key);
-    // owner of every unique node: block, thread, plane, component
+    std::copy(key, key + 16, f->key);
+    const int NT = g.nt;
+    // every (block, thread) whose extended region holds a node: the node's
+    // plane and component
     struct Own { int64_t blk; int tid; int x; int comp; int node; };
-    std::vector<Own> own((size_t)nnodes);
+    std::vector<Own> own;
+    own.reserve((size_t)nnodes);
+    const int ez = 4 * g.ez4;
     for (int k = 0; k < nnodes; ++k) {
         const int64_t o = h_noff[(size_t)k];
         const int x = (int)(o / L.sx);
         const int64_t rem = o % L.sx;
         const int y = (int)(rem / L.sy), z = (int)(rem % L.sy);
-        const int itz = z / TZ, ity = y / TY, ich = x / p.cx;
-        const int64_t b = ((int64_t)ich * p.nty + ity) * p.ntz + itz;
-        const int zz = z - itz * TZ;
-        own[(size_t)k] = {b, (y - ity * TY) * ts.bz + zz / 4, x, zz % 4, k};
+        const int ich0 = std::max(0, (x - g.ex) / g.cx - 1), ich1 = std::min(g.nchunks - 1, (x + g.ex) / g.cx + 1);
+        const int ity0 = std::max(0, (y - g.ey) / g.ty - 1), ity1 = std::min(g.nty - 1, (y + g.ey) / g.ty + 1);
+        const int itz0 = std::max(0, (z - ez) / g.tz - 1), itz1 = std::min(g.ntz - 1, (z + ez) / g.tz + 1);
+        for (int ich = ich0; ich <= ich1; ++ich) {
+            const int xb = ich * g.cx, xe = std::min(xb + g.cx, L.nx);
+            if (x < xb - g.ex || x >= xe + g.ex) continue;
+            for (int ity = ity0; ity <= ity1; ++ity) {
+                const int yl = y - (ity * g.ty - g.ey);
+                if (yl < 0 || yl >= g.ty + 2 * g.ey) continue;
+                for (int itz = itz0; itz <= itz1; ++itz) {
+                    const int zl = z - (itz * g.tz - ez);
+                    if (zl < 0 || zl >= g.tz + 2 * ez) continue;
+                    const int64_t b = ((int64_t)ich * g.nty + ity) * g.ntz + itz;
+                    own.push_back({b, (yl + g.oy) * g.bz + zl / 4 + g.oz4, x, zl % 4, k});
+                }
+            }
+        }
     }
     std::sort(own.begin(), own.end(), [](const Own& a, const Own& b) {
         if (a.blk != b.blk) return a.blk < b.blk;
@@ -420,14 +454,14 @@ wf_status PointSet::fused(const Layout& L, const StepParams& p, const FusedInj**
     });
     // entries: one per (block, thread, plane), 4 increment slots each (the
     // thread's 4 z nodes; an empty slot has no terms and so a zero increment)
-    std::vector<int> blk((size_t)p.nblocks + 1, 0), xs, segs(1, 0), pts;
-    std::vector<int2> thr((size_t)p.nblocks * NT, make_int2(0, 0));
+    std::vector<int> blk((size_t)g.nblocks + 1, 0), xs, segs(1, 0), pts;
+    std::vector<int2> thr((size_t)g.nblocks * NT, make_int2(0, 0));
     std::vector<int64_t> offs;
     std::vector<float> etas, ws;
     f->ok = true;
     size_t i = 0;
     int ne = 0;
-    for (int64_t b = 0; b < p.nblocks; ++b) {
+    for (int64_t b = 0; b < g.nblocks; ++b) {
         blk[(size_t)b] = ne;
         const int e_b0 = ne;
         while (i < own.size() && own[i].blk == b) {
@@ -460,9 +494,9 @@ wf_status PointSet::fused(const Layout& L, const StepParams& p, const FusedInj**
             }
             thr[(size_t)(b * NT + tid)] = make_int2(t0, ne);
         }
-        if (ne - e_b0 > inj_cap(L.ndim)) f->ok = false;
+        if (ne - e_b0 > g.cap) f->ok = false;
     }
-    blk[(size_t)p.nblocks] = ne;
+    blk[(size_t)g.nblocks] = ne;
     f->nentries = ne;
     f->nnodes = 4 * ne;
     wf_status st;
@@ -525,6 +559,19 @@ wf_status Model::init(const wf_geom* g, const float* m_dev, hipStream_t s) {
     if (st != WF_OK) return st;
     if ((st = d_scratch.alloc(256)) != WF_OK) return st;
     return set_m(m_dev, s);
+}
+
+wf_status Model::ensure_u2(hipStream_t s) {
+    if (d_u2[0].ptr && d_u2[1].ptr) return WF_OK;
+    const int64_t fb = L.field_bytes();
+    wf_status st;
+    for (DevBuf& b : d_u2) {
+        if (b.ptr) continue;
+        if ((st = b.alloc(fb)) != WF_OK) return st;
+        // ghost planes and pads must read as zero
+        if ((st = hip_check(launch_fill(b.f(), b.bytes / 4, 0.0f, s), "fill")) != WF_OK) return st;
+    }
+    return WF_OK;
 }
 
 wf_status Model::init_pending(const wf_geom* g, const float* m_dev, hipStream_t s, unsigned int* host3) {

@@ -51,6 +51,7 @@ struct ScratchRegion {
 };
 void set_thread_scratch(ScratchRegion* r);
 bool thread_scratch_active();
+bool thread_arena_active();
 
 // Pinned host memory for the small uploads of one thread: while set, a
 // DevBuf::upload that fits copies its data here and queues an asynchronous
@@ -113,8 +114,23 @@ struct Layout {
 // launch plan: entries (one per owning thread and plane, holding that
 // thread's 4 z nodes) grouped by block, by thread and by x inside a block,
 // plus everything the increment kernel needs per node slot in that order.
+// Where a launch's threads sit: block b = (chunk * nty + ity) * ntz + itz
+// covers the inner tile [ity ty, (ity + 1) ty) x [itz tz, (itz + 1) tz) and
+// planes [chunk cx, min((chunk + 1) cx, nx)), each extended by ey rows, 4 ez4
+// nodes and ex planes on either side (clipped to the grid); the node at row
+// r and float4 column c of that region belongs to thread (r + oy) bz + c +
+// oz4, which holds the 4 z nodes of its float4 column. A node inside several
+// blocks' extended regions gets an entry in each.
+struct InjGeom {
+    int tz = 0, ty = 0, bz = 0, nt = 0;
+    int ey = 0, ez4 = 0, ex = 0;
+    int oy = 0, oz4 = 0;
+    int ntz = 0, nty = 0, cx = 0, nchunks = 0, nblocks = 0;
+    int cap = 0;                           // entries a block can stage
+    int tag = 0;                           // distinguishes plans of different kernels
+};
 struct FusedInj {
-    int64_t key[6] = {0, 0, 0, 0, 0, 0};   // plan: tile, ntz, nty, cx, nchunks, NT
+    int64_t key[16] = {};                  // the InjGeom it was built for
     bool ok = false;                       // false: a block exceeds the LDS cap
     int nentries = 0;                      // (thread, plane) entries
     int nnodes = 0;                        // increment slots: 4 per entry
@@ -137,6 +153,7 @@ struct PointSet {
     wf_status build(const wf_geom* g, const Layout& L, int npts, const double* xyz);
     // tables for the fused injection of launch plan p (nullptr on failure)
     wf_status fused(const Layout& L, const StepParams& p, const FusedInj** out) const;
+    wf_status fused(const Layout& L, const InjGeom& g, const FusedInj** out) const;
     PointSet() = default;
     PointSet(const PointSet&) = delete;
     PointSet& operator=(const PointSet&) = delete;
@@ -168,7 +185,8 @@ struct Model : public wf_model {
     wf::Layout L;
     double alpha[wf::kMaxHalf + 1]{};
     wf::DevBuf d_m, d_kap, d_u[2], d_eta_pack, d_etax, d_etay, d_etaz, d_scratch;
-    wf::DevBuf d_inc[2];   // precomputed injection increments (grow-only, stream-ordered reuse)
+    wf::DevBuf d_u2[2];    // the two-update loop's second pair of fields (made on first use)
+    wf::DevBuf d_inc[3];   // precomputed injection increments (grow-only, stream-ordered reuse)
     wf::DevBuf ws;         // gradient workspace (checkpoint pool + adjoint pair), kept between calls
     bool ws_clean = false; // every ghost plane in ws is zero
     float m_min = 0.f, m_max = 0.f;
@@ -224,9 +242,12 @@ struct Model : public wf_model {
     // plan a step launch; sample_points > 0 leaves room for that many fused samples
     void fill_step(wf::StepParams& p, double dt, int mode = wf::kModePlain) const;
     float* u(int i) const { return L.field(d_u[i].ptr); }
+    // fields 2 and 3 of the two-update loop (allocated, ghost planes zeroed, on first use)
+    wf_status ensure_u2(hipStream_t s);
+    float* u2(int i) const { return L.field(d_u2[i].ptr); }
     float* kap() const { return L.field(d_kap.ptr); }
     int64_t bytes() const {
-        return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_eta_pack.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes + ws.bytes;
+        return d_m.bytes + d_kap.bytes + d_u[0].bytes + d_u[1].bytes + d_u2[0].bytes + d_u2[1].bytes + d_eta_pack.bytes + d_scratch.bytes + d_inc[0].bytes + d_inc[1].bytes + d_inc[2].bytes + ws.bytes;
     }
 };
 
@@ -245,17 +266,22 @@ struct ProfScope {
 // and one after its last (finish(n) with the loop's n step launches).
 struct RunSpan {
     hipStream_t s;
+    int kind;
     hipEvent_t a = nullptr, b = nullptr;
-    explicit RunSpan(hipStream_t s);
+    explicit RunSpan(hipStream_t s, int kind = WF_KERNEL_STEP_RUN);
     void finish(int64_t launches);
     ~RunSpan();
 };
-// Every step launch is counted per kernel mode (wf_profile_step_launches).
+// Every step launch is counted per kernel mode (wf_profile_step_launches);
+// mode kModeCount counts the two-update launches.
 void count_step_launch(int mode);
 
 // Time loops (propagate.cpp).
 // Process-wide switch for capturing time loops as HIP graphs.
 void set_graphs_enabled(bool on);
+// Process-wide mode of two updates per launch in 3D forward loops: 0 off,
+// 1 where measured faster (step2_preferred), 2 wherever compiled.
+void set_two_step_mode(int mode);
 // While positive on a thread, the time loops that thread enqueues keep at
 // most about 2 x `steps` step launches queued ahead of the device (a host
 // wait on an event every `steps` launches), so that work other streams

@@ -179,3 +179,13 @@ def test_validation_switch():
     from paper_1808_01995_amd import _abi
     assert _abi.lib.wf_validate_enable(1) == _abi.WF_OK
     assert _abi.lib.wf_validate_enable(0) == _abi.WF_OK
+
+
+def test_two_step_mode_switch():
+    """The mode of two updates per launch takes 0, 1 or 2; anything else is
+    an argument error that leaves the mode unchanged (pure host call)."""
+    from paper_1808_01995_amd import _abi
+    for bad in (-1, 3, 100):
+        assert _abi.lib.wf_two_step_enable(bad) == _abi.WF_E_ARG
+    for mode in (0, 2, 1):
+        assert _abi.lib.wf_two_step_enable(mode) == _abi.WF_OK

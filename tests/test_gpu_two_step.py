@@ -1,0 +1,114 @@
+"""Two updates per launch (3D forward loops of space order 4 and 8).
+
+The two-update kernel forms every node of u^{n+1} (on its tile extended by M
+rows, 4 ceil(M/4) z nodes and M planes) and of u^{n+2} with the arithmetic of
+the single-update kernel in the same order, so records and saved fields must
+equal the one-update-per-launch loop bit for bit: compared here with torch.equal
+for both orders, odd and even update counts, x chunks of every length the
+planner picks, many sources scattered over tile, chunk and grid edges, and
+more receivers than blocks. The same runs stay within the record bar of the
+FP64 oracle, and the fields' ghost planes stay zero.
+"""
+import numpy as np
+import pytest
+
+from _harness import check_record, make_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _forward(P, two, prop=None, save_every=None, src=None, q=None, rec=None):
+    from paper_1808_01995_amd import _abi
+    prop = prop or P.propagator()
+    src = P.src_xyz if src is None else src
+    q = P.q32 if q is None else q
+    rec = P.rec_xyz if rec is None else rec
+    _abi.wf_two_step_enable(2 if two else 0)
+    try:
+        _abi.wf_profile_step_launches(0, reset=True)
+        out = prop.forward(P.dt, P.nt, src, torch.from_numpy(q).cuda(), rec, save_every=save_every)
+        torch.cuda.synchronize()
+        n1 = _abi.wf_profile_step_launches(0)
+        n2 = _abi.wf_profile_step_launches(_abi.WF_STEP_LAUNCHES_TWO)
+    finally:
+        _abi.wf_two_step_enable(1)
+    return out, n1, n2
+
+
+def _scatter_sources(P, n, seed):
+    """n sources: random nodes and cell interiors, plus the grid's corners
+    and points just inside the physical grid's faces."""
+    rng = np.random.default_rng(seed)
+    nd = len(P.shape_phys)
+    h = np.asarray(P.spacing)
+    lo = -P.nbl * h
+    hi = (np.asarray(P.shape_phys) - 1 + P.nbl) * h
+    pts = [rng.uniform(lo, hi) for _ in range(n - 4)]
+    pts.append(lo.copy())                   # first node of the computational grid
+    pts.append(hi.copy())                   # last node
+    pts.append(np.zeros(nd))                # the physical grid's corner
+    pts.append((np.asarray(P.shape_phys) - 1) * h - 0.3 * h)
+    src = np.stack(pts)
+    q = np.stack([np.sin(0.07 * (i + 1) * np.arange(P.nt)) * (1.0 + 0.1 * i) for i in range(n)], axis=1)
+    return src, q.astype(np.float32)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("steps", [1, 2, 3, 8, 9])
+def test_two_step_equals_one_update_per_launch(k, steps):
+    """Records bitwise equal with two updates per launch and with one, for
+    1 (no two-update launch), 2, 3, 8 and 9 updates; the launch counts show
+    which kernel ran. 56 x 33 x 131 computational nodes at order 8 (2 z tiles,
+    the second ragged; 3 y tiles, the last ragged; x chunks of a few planes)."""
+    P = make_problem((40, 17, 115), 8, k, steps, seed=200 + k + steps, nrec=70)
+    src, q = _scatter_sources(P, 24, seed=k + steps)
+    rec = np.vstack([P.rec_xyz, src])   # receivers on the sources see every update
+    prop = P.propagator()
+    d2, n1a, n2a = _forward(P, True, prop=prop, src=src, q=q, rec=rec)
+    d1, n1b, n2b = _forward(P, False, prop=prop, src=src, q=q, rec=rec)
+    assert (n2a, n1a) == (steps // 2, steps % 2), (n2a, n1a)
+    assert (n2b, n1b) == (0, steps), (n2b, n1b)
+    assert torch.equal(d2, d1), float((d2 - d1).abs().max())
+    if steps >= 2:   # q^0 = 0: u^1 is zero, u^2 is not at the sources
+        assert float(d1[-1, P.rec_xyz.shape[0]:].abs().max()) > 0
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_two_step_saved_fields_and_oracle(k):
+    """Saved wavefields (every update and every third) bitwise equal to the
+    one-update loop's, the record within the oracle's bar, and the model's
+    ghost planes (those of the second field pair included) still zero."""
+    from paper_1808_01995_amd import _abi
+    P = make_problem((30, 22, 126), 6, k, 11, seed=230 + k, nrec=50)
+    prop = P.propagator()
+    for every in (1, 3):
+        (d2, u2), _, n2 = _forward(P, True, prop=prop, save_every=every)
+        (d1, u1), _, _ = _forward(P, False, prop=prop, save_every=every)
+        assert n2 == 5
+        assert torch.equal(d2, d1)
+        assert torch.equal(u2, u1), float((u2 - u1).abs().max())
+    check_record(d2.cpu().numpy(), P.oracle_forward(), label="two updates per launch, order %d" % k)
+    assert _abi.wf_model_ghost_nonzero(prop.handle) == 0
+
+
+def test_two_step_many_blocks_and_receivers():
+    """A grid of many tiles in one or two chunks (100 x 120 x 250 nodes at
+    order 8) with more receivers than blocks: records bitwise equal to the
+    one-update loop's over 40 updates."""
+    P = make_problem((84, 104, 234), 8, 8, 40, seed=251, nrec=900)
+    src, q = _scatter_sources(P, 12, seed=9)
+    prop = P.propagator()
+    d2, _, n2 = _forward(P, True, prop=prop, src=src, q=q)
+    d1, _, _ = _forward(P, False, prop=prop, src=src, q=q)
+    assert n2 == 20
+    assert torch.equal(d2, d1), float((d2 - d1).abs().max())
+
+
+def test_two_step_off_for_other_orders_and_2d():
+    """Orders other than 4 and 8, and 2D grids, keep one update per launch."""
+    for shape, k in (((30, 20, 40), 12), ((60, 70), 8)):
+        P = make_problem(shape, 6, k, 6, seed=270 + k, nrec=20)
+        _, n1, n2 = _forward(P, True)
+        assert (n1, n2) == (6, 0)
