@@ -272,7 +272,9 @@ def slab_share(torch, ngpu=8, steps=300, so=8):
 def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
     """512^3 physical (592^3 computational), two-layer 1.5/2.5 km/s, one
     shot per order: GPts/s and the step kernel's algorithmic bandwidth (the
-    shot's run of step launches timed by one pair of HIP events)."""
+    shot's run of step launches timed by one pair of HIP events). Where the
+    default runs two updates per launch (order 4 at this size) the same shot
+    also runs with one update per launch, for comparison."""
     from paper_1808_01995_amd import Propagator, _abi
     from synthetic import config, ricker
     res = []
@@ -286,21 +288,37 @@ def sweep_c3(torch, orders=(4, 8, 12, 16), steps=500):
         dt = 0.5 * prop.critical_dt()
         q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
         rec = torch.empty((c.nt, c.rec.shape[0]), device="cuda")
-        prop.forward(dt, 21, c.src, q[:21].contiguous(), c.rec, rec_out=rec[:21])   # warm-up
-        _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
-        _abi.wf_profile_runs_enable(True)
-        el, _ = _timed(torch, lambda: prop.forward(dt, c.nt, c.src, q, c.rec, rec_out=rec))
-        _abi.wf_profile_runs_enable(False)
-        ms, n = _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
-        us = ms / max(n, 1) * 1e3
-        gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
-        if stream is None:
-            stream = _abi.wf_stream_bandwidth(prop.npoints, 10)
-        res.append({"space_order": so, "dt_ms": round(dt, 4), "gpts": round(prop.npoints * c.steps / el / 1e9, 1),
-                    "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs), "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3),
-                    "frac_of_stream": round(gbs / stream, 3)})
+        for mode in (1, 0):
+            _abi.wf_two_step_enable(mode)
+            prop.forward(dt, 21, c.src, q[:21].contiguous(), c.rec, rec_out=rec[:21])   # warm-up
+            _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
+            _abi.wf_profile_runs_enable(True)
+            el, _ = _timed(torch, lambda: prop.forward(dt, c.nt, c.src, q, c.rec, rec_out=rec))
+            _abi.wf_profile_runs_enable(False)
+            ms1, n1 = _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN)
+            ms2, n2 = _abi.wf_profile_read(_abi.WF_KERNEL_STEP2_RUN, reset=True)
+            # per update: the summed spans over the updates they cover
+            us = (ms1 + ms2) / max(n1 + 2 * n2, 1) * 1e3
+            gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
+            if stream is None:
+                stream = _abi.wf_stream_bandwidth(prop.npoints, 10)
+            r = {"space_order": so, "dt_ms": round(dt, 4), "gpts": round(prop.npoints * c.steps / el / 1e9, 1),
+                 "updates_per_launch": 2 if n2 else 1,
+                 "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs), "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3),
+                 "frac_of_stream": round(gbs / stream, 3)}
+            if n2:
+                two_us = ms2 / n2 * 1e3
+                r.update({"step_kernel_us_note": "per update; 16 B per node per update",
+                          "two_update_launch_us": round(two_us, 1),
+                          "two_update_frac_8TBs": round(20.0 * prop.npoints / (two_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 3),
+                          "two_update_note": "its own 20 B per node per launch (read u^n, u^{n-1}, kappa; "
+                                             "write u^{n+1}, u^{n+2})"})
+            res.append(r)
+            log("c3 so%d: %s" % (so, res[-1]))
+            if not n2:
+                break   # one update per launch by default: nothing to compare
+        _abi.wf_two_step_enable(1)
         prop.close()
-        log("c3 so%d: %s" % (so, res[-1]))
     return {"workload": "592^3 computational (512^3 + 40-node layer), two-layer 1.5/2.5 km/s, %d updates" % steps,
             "stream_GBs": round(stream, 1), "orders": res}
 

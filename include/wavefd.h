@@ -181,8 +181,8 @@ wf_status wf_validate_enable(int on);
  * kept while it is off and used again once it is switched back on. */
 wf_status wf_graph_enable(int on);
 
-/* Process-wide mode for running the time loop of wf_forward on 3D models of
- * space order 4 or 8 two updates (eq. eulerfwd with the damping of eq.
+/* Process-wide mode for running the time loops of wf_forward and wf_adjoint
+ * on 3D models of space order 4 or 8 two updates (eq. eulerfwd with the damping of eq.
  * fdWE-abc, applied twice) per kernel launch: the launch reads u^n, u^{n-1}
  * and kappa once and writes u^{n+1} and u^{n+2}, 20 bytes per node for two
  * updates instead of 32 (the update is bound by memory traffic, Section
@@ -358,7 +358,7 @@ int64_t wf_revolve_schedule(int64_t steps, int snaps, int32_t* kind, int64_t* at
                                  or adjoint time loop (wf_profile_runs_enable) */
 #define WF_KERNEL_STEP2   4   /* the two-update kernel (wf_two_step_enable)    */
 #define WF_KERNEL_STEP2_RUN 5 /* the run of two-update launches of a forward
-                                 time loop (wf_profile_runs_enable)           */
+                                 or adjoint time loop (wf_profile_runs_enable) */
 
 /* While enabled (process-wide), launches of the kernels WF_KERNEL_STEP,
  * WF_KERNEL_INJECT, WF_KERNEL_SAMPLE and WF_KERNEL_STEP2 are
@@ -373,7 +373,7 @@ wf_status wf_profile_enable(int on);
  * launch count is the number of step launches those spans cover, so that the
  * summed time over the count is the average duration of one step launch
  * (gaps between the back-to-back launches included) with two events per
- * loop. A forward loop that runs two updates per launch records its run of
+ * loop. A loop that runs two updates per launch records its run of
  * two-update launches as kind WF_KERNEL_STEP2_RUN the same way (and any
  * single update left over as WF_KERNEL_STEP_RUN). Like per-launch timing, it
  * suspends graph capture. */
@@ -388,8 +388,8 @@ wf_status wf_profile_read(int kind, double* total_ms, int64_t* launches, int res
  * `mode`: 0 the plain update (forward and adjoint steps, the gradient's
  * forward and recomputed steps), 1 the update with imaging (the gradient's
  * reverse steps), 2 the Born background step, 3 the Born scattered step, 4
- * the two-update launches of forward loops (each advancing two plain
- * updates).
+ * the two-update launches of forward and adjoint loops (each advancing two
+ * plain updates).
  * Counted on the host for every launch, whether timing is on or not; reset
  * != 0 clears every mode after reading. Batched launches of the serving
  * engine are not counted. */

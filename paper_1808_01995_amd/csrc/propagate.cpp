@@ -310,26 +310,25 @@ void set_thread_throttle(int steps) {
     t_thr.armed[0] = t_thr.armed[1] = false;
 }
 
-wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
-                      const PointSet& rec, float* rec_out, float* u_save, int save_every,
-                      hipStream_t s, DevBuf* inc_buf) {
-    const Layout& L = md.L;
-    WF_TRY(md.ensure_kap(dt, s));
-    StepParams p;
-    md.fill_step(p, dt, false);
-    Injector inj;
-    WF_TRY(inj.plan(md, src, p, src_wav, nt, inc_buf ? *inc_buf : md.d_inc[0], s));
+namespace {
 
-    // Two updates per launch (3D, compiled orders) for loops of two updates
-    // or more; calls that allocate from an arena or a fixed scratch keep one.
+// Two updates per launch (3D, compiled orders) for loops of two updates or
+// more, where the mode allows it; calls that allocate from an arena or a
+// fixed scratch keep one. `pts` are the points injected (sources of a
+// forward loop, receivers of an adjoint one), `smp` the points sampled.
+struct TwoStep {
+    bool on = false;
     Step2Params p2{};
-    Injector inj2[2];
-    const int two_mode = two_step_switch().load(std::memory_order_relaxed);
-    bool two = nt >= 3 && step2_supported(L.ndim, md.half) &&
-               (two_mode == 2 || (two_mode == 1 && step2_preferred(L.ndim, md.half, L.npoints))) &&
-               !thread_arena_active() && !thread_scratch_active() &&
-               !(src.nnodes > 0 && fused_injection_disabled());
-    if (two) {
+    Injector inj[2];   // [0]: the first update's extended tile, [1]: the second's inner tile
+    wf_status plan(Model& md, const StepParams& p, int nt, const PointSet& pts, const float* series,
+                   const PointSet& smp, hipStream_t s) {
+        const Layout& L = md.L;
+        const int mode = two_step_switch().load(std::memory_order_relaxed);
+        on = nt >= 3 && step2_supported(L.ndim, md.half) &&
+             (mode == 2 || (mode == 1 && step2_preferred(L.ndim, md.half, L.npoints))) &&
+             !thread_arena_active() && !thread_scratch_active() &&
+             !(pts.nnodes > 0 && fused_injection_disabled());
+        if (!on) return WF_OK;
         p2.kap = p.kap;
         p2.etax = p.etax;
         p2.etay = p.etay;
@@ -345,7 +344,7 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
         std::copy(p.wz, p.wz + kMaxHalf + 1, p2.wz);
         p2.inv2dt = p.inv2dt;
         step2_plan(p2, md.half, 0);
-        if (src.nnodes > 0) {
+        if (pts.nnodes > 0) {
             const int M = md.half, hz = step2_ext_cols(M);
             InjGeom g;
             g.tz = 4 * (kStep2Cols - 2 * hz);
@@ -366,29 +365,83 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
             InjGeom gi = g;   // second update: the inner tile, numbered in the extended one
             gi.oy = M;
             gi.oz4 = hz;
-            WF_TRY(inj2[0].plan(md, src, p, src_wav, nt, md.d_inc[1], s, &ge));
-            WF_TRY(inj2[1].plan(md, src, p, src_wav, nt, md.d_inc[2], s, &gi));
-            two = inj2[0].fz && inj2[1].fz;
+            WF_TRY(inj[0].plan(md, pts, p, series, nt, md.d_inc[1], s, &ge));
+            WF_TRY(inj[1].plan(md, pts, p, series, nt, md.d_inc[2], s, &gi));
+            on = inj[0].fz && inj[1].fz;
+            if (!on) return WF_OK;
         }
-        if (two) WF_TRY(md.ensure_u2(s));
+        if (smp.npts > 0) {
+            p2.smp_off = smp.d_off.as<int64_t>();
+            p2.smp_w = smp.d_w.f();
+            p2.smp_n = smp.npts;
+            p2.smp_per = (int)(((int64_t)smp.npts + p2.nblocks - 1) / p2.nblocks);
+        }
+        return md.ensure_u2(s);
     }
-    if (rec.npts > 0) {
-        p2.smp_off = rec.d_off.as<int64_t>();
-        p2.smp_w = rec.d_w.f();
-        p2.smp_n = rec.npts;
-        p2.smp_per = p2.nblocks > 0 ? (int)(((int64_t)rec.npts + p2.nblocks - 1) / p2.nblocks) : 0;
+    void key(std::vector<int64_t>& v, const Model& md) const {
+        v.push_back(on ? 1 : 0);
+        if (!on) return;
+        for (int64_t x : {(int64_t)p2.cx, (int64_t)(intptr_t)md.u2(0), (int64_t)(intptr_t)md.u2(1),
+                          (int64_t)(intptr_t)inj[0].inc, (int64_t)(intptr_t)inj[1].inc,
+                          (int64_t)(intptr_t)inj[0].fz, (int64_t)(intptr_t)inj[1].fz})
+            v.push_back(x);
     }
+    // device side: the increments of every step of both tables
+    wf_status enqueue(hipStream_t q) const {
+        WF_TRY(inj[0].enqueue(q));
+        return inj[1].enqueue(q);
+    }
+    // one launch: out1 = S(cur, old) + increments of row r1, out2 = S(out1,
+    // cur) + those of row r2; samples of cur and old into smp_cur / smp_old
+    wf_status launch(const Model& md, const float* cur, const float* old, float* out1, float* out2,
+                     int64_t r1, int64_t r2, float* smp_cur, float* smp_old, hipStream_t q) const {
+        Step2Params x = p2;
+        x.cur = cur;
+        x.old = old;
+        x.out1 = out1;
+        x.out2 = out2;
+        x.smp_cur = p2.smp_n > 0 ? smp_cur : nullptr;
+        x.smp_old = p2.smp_n > 0 ? smp_old : nullptr;
+        const int64_t rows[2] = {r1, r2};
+        for (int k = 0; k < 2; ++k) {
+            x.inj_blk[k] = nullptr;
+            const Injector& ik = inj[k];
+            if (!ik.fz) continue;
+            x.inj_blk[k] = ik.fz->blk.as<int>();
+            x.inj_thr[k] = ik.fz->thr.as<int2>();
+            x.inj_x[k] = ik.fz->x.as<int>();
+            x.inj_inc[k] = reinterpret_cast<const float4*>(ik.inc + rows[k] * ik.fz->nnodes);
+        }
+        count_step_launch(kModeCount);
+        {
+            ProfScope prof(WF_KERNEL_STEP2, q);
+            WF_TRY(hip_check(launch_step2(x, md.half, q), "two-update launch"));
+        }
+        return throttle_tick(q);
+    }
+};
+
+}  // namespace
+
+wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const float* src_wav,
+                      const PointSet& rec, float* rec_out, float* u_save, int save_every,
+                      hipStream_t s, DevBuf* inc_buf) {
+    const Layout& L = md.L;
+    WF_TRY(md.ensure_kap(dt, s));
+    StepParams p;
+    md.fill_step(p, dt, false);
+    Injector inj;
+    WF_TRY(inj.plan(md, src, p, src_wav, nt, inc_buf ? *inc_buf : md.d_inc[0], s));
+
+    TwoStep two;
+    WF_TRY(two.plan(md, p, nt, src, src_wav, rec, s));
 
     GraphKey key;
     key.v = {0, (int64_t)nt, bits_of(dt), src.gen, rec.gen, (int64_t)(intptr_t)src_wav,
              (int64_t)(intptr_t)rec_out, (int64_t)(intptr_t)u_save, save_every, p.cx, p.tile,
              (int64_t)(intptr_t)inj.inc, (int64_t)(intptr_t)inj.fz, (int64_t)(intptr_t)md.u(0),
-             (int64_t)(intptr_t)md.u(1), (int64_t)(intptr_t)md.kap(), two ? 1 : 0};
-    if (two)
-        for (int64_t v : {(int64_t)p2.cx, (int64_t)(intptr_t)md.u2(0), (int64_t)(intptr_t)md.u2(1),
-                          (int64_t)(intptr_t)inj2[0].inc, (int64_t)(intptr_t)inj2[1].inc,
-                          (int64_t)(intptr_t)inj2[0].fz, (int64_t)(intptr_t)inj2[1].fz})
-            key.v.push_back(v);
+             (int64_t)(intptr_t)md.u(1), (int64_t)(intptr_t)md.kap()};
+    two.key(key.v, md);
     auto enqueue = [&](hipStream_t q) -> wf_status {
         float* A = md.u(0);   // u^n
         float* B = md.u(1);   // u^{n-1}, overwritten by u^{n+1}
@@ -398,38 +451,18 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
         WF_TRY(inj.enqueue(q));
         if (nt == 1 && rec.npts > 0) WF_TRY(hip_check(launch_fill(rec_out, rec.npts, 0.0f, q), "fill"));
         int n = 0;
-        if (two) {
+        if (two.on) {
             // launch at n: u^{n+1} and u^{n+2} from u^n and u^{n-1}; q^n and
             // q^{n+1} injected; d^n and d^{n-1} sampled from the fields it reads
-            WF_TRY(inj2[0].enqueue(q));
-            WF_TRY(inj2[1].enqueue(q));
+            WF_TRY(two.enqueue(q));
             float* C = md.u2(0);
             float* D = md.u2(1);
-            Step2Params q2 = p2;
             RunSpan span2(q, WF_KERNEL_STEP2_RUN);
             int launches = 0;
             for (; n + 2 < nt; n += 2) {
-                q2.cur = A;
-                q2.old = B;
-                q2.out1 = C;
-                q2.out2 = D;
-                q2.smp_cur = rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr;
-                q2.smp_old = (rec.npts && n >= 1) ? rec_out + (int64_t)(n - 1) * rec.npts : nullptr;
-                for (int k = 0; k < 2; ++k) {
-                    const Injector& ik = inj2[k];
-                    q2.inj_blk[k] = nullptr;
-                    if (!ik.fz) continue;
-                    q2.inj_blk[k] = ik.fz->blk.as<int>();
-                    q2.inj_thr[k] = ik.fz->thr.as<int2>();
-                    q2.inj_x[k] = ik.fz->x.as<int>();
-                    q2.inj_inc[k] = reinterpret_cast<const float4*>(ik.inc + (int64_t)(n + k) * ik.fz->nnodes);
-                }
-                count_step_launch(kModeCount);
-                {
-                    ProfScope prof(WF_KERNEL_STEP2, q);
-                    WF_TRY(hip_check(launch_step2(q2, md.half, q), "two-update launch"));
-                }
-                WF_TRY(throttle_tick(q));
+                float* dc = rec.npts ? rec_out + (int64_t)n * rec.npts : nullptr;
+                float* dold = (rec.npts && n >= 1) ? rec_out + (int64_t)(n - 1) * rec.npts : nullptr;
+                WF_TRY(two.launch(md, A, B, C, D, n, n + 1, dc, dold, q));
                 ++launches;
                 if (u_save && (n + 1) % save_every == 0)
                     WF_TRY(hip_check(launch_unpitch(C, u_save + (int64_t)((n + 1) / save_every) * L.npoints,
@@ -442,7 +475,7 @@ wf_status run_forward(Model& md, double dt, int nt, const PointSet& src, const f
             }
             span2.finish(launches);
             // d^{n-1} is in the old field, which the loop below overwrites
-            if (n >= 1) WF_TRY(sample(rec, B, rec_out + (int64_t)(n - 1) * rec.npts, q));
+            WF_TRY(sample(rec, B, rec_out + (int64_t)(n - 1) * rec.npts, q));
         }
         StepParams ps = p;
         RunSpan span(q);
@@ -474,11 +507,14 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
     md.fill_step(p, dt, false);
     Injector inj;
     WF_TRY(inj.plan(md, rec, p, rec_in, nt, md.d_inc[0], s));
+    TwoStep two;
+    WF_TRY(two.plan(md, p, nt, rec, rec_in, src, s));
     GraphKey key;
     key.v = {1, (int64_t)nt, bits_of(dt), rec.gen, src.gen, (int64_t)(intptr_t)rec_in,
              (int64_t)(intptr_t)src_out, 0, 0, p.cx, p.tile, (int64_t)(intptr_t)inj.inc,
              (int64_t)(intptr_t)inj.fz, (int64_t)(intptr_t)md.u(0), (int64_t)(intptr_t)md.u(1),
              (int64_t)(intptr_t)md.kap()};
+    two.key(key.v, md);
     auto enqueue = [&](hipStream_t q) -> wf_status {
         float* A = md.u(0);   // v^{n+1}
         float* B = md.u(1);   // v^{n+2}, overwritten by v^n
@@ -486,17 +522,40 @@ wf_status run_adjoint(Model& md, double dt, int nt, const PointSet& rec, const f
         WF_TRY(hip_check(launch_fill(B, L.elems, 0.0f, q), "fill"));
         WF_TRY(inj.enqueue(q));
         if (nt == 1 && src.npts > 0) WF_TRY(hip_check(launch_fill(src_out, src.npts, 0.0f, q), "fill"));
+        int n = nt - 2;
+        if (two.on) {
+            // launch at n: v^n and v^{n-1} from v^{n+1} and v^{n+2}; y^{n+1}
+            // and y^n injected; x^{n+1} and x^{n+2} sampled from the fields it reads
+            WF_TRY(two.enqueue(q));
+            float* C = md.u2(0);
+            float* D = md.u2(1);
+            RunSpan span2(q, WF_KERNEL_STEP2_RUN);
+            int launches = 0;
+            for (; n >= 1; n -= 2) {
+                float* xc = src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr;
+                float* xo = (src.npts && n + 2 <= nt - 1) ? src_out + (int64_t)(n + 2) * src.npts : nullptr;
+                WF_TRY(two.launch(md, A, B, C, D, n + 1, n, xc, xo, q));
+                ++launches;
+                std::swap(A, D);   // v^{n-1}
+                std::swap(B, C);   // v^n
+            }
+            span2.finish(launches);
+            // x^{n+2} is in the old field, which the loop below overwrites
+            WF_TRY(sample(src, B, src_out + (int64_t)(n + 2) * src.npts, q));
+        }
         StepParams ps = p;
         RunSpan span(q);
-        for (int n = nt - 2; n >= 0; --n) {
+        int singles = 0;
+        for (; n >= 0; --n) {
             // step n: v^n from v^{n+1}, v^{n+2}; y^{n+1} injected; x^{n+1} = P_s v^{n+1} sampled
             inj.configure(ps, n + 1);
             set_sampling(ps, &src, src.npts ? src_out + (int64_t)(n + 1) * src.npts : nullptr);
             WF_TRY(step(ps, md, A, B, B, kModePlain, nullptr, nullptr, q));
             WF_TRY(inj.after(md, n + 1, B, nullptr, nullptr, ps, q));
             std::swap(A, B);
+            ++singles;
         }
-        span.finish(nt - 1);
+        span.finish(singles);
         if (nt > 1) WF_TRY(sample(src, A, src_out, q));
         return WF_OK;
     };

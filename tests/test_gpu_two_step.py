@@ -1,4 +1,4 @@
-"""Two updates per launch (3D forward loops of space order 4 and 8).
+"""Two updates per launch (3D forward and adjoint loops of space order 4 and 8).
 
 The two-update kernel forms every node of u^{n+1} (on its tile extended by M
 rows, 4 ceil(M/4) z nodes and M planes) and of u^{n+2} with the arithmetic of
@@ -112,3 +112,40 @@ def test_two_step_off_for_other_orders_and_2d():
         P = make_problem(shape, 6, k, 6, seed=270 + k, nrec=20)
         _, n1, n2 = _forward(P, True)
         assert (n1, n2) == (6, 0)
+
+
+def _adjoint(P, two, prop, rec, y, src):
+    from paper_1808_01995_amd import _abi
+    _abi.wf_two_step_enable(2 if two else 0)
+    try:
+        _abi.wf_profile_step_launches(0, reset=True)
+        x = prop.adjoint(P.dt, P.nt, rec, torch.from_numpy(y).cuda(), src)
+        torch.cuda.synchronize()
+        n2 = _abi.wf_profile_step_launches(_abi.WF_STEP_LAUNCHES_TWO)
+    finally:
+        _abi.wf_two_step_enable(1)
+    return x, n2
+
+
+@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("steps", [2, 3, 10])
+def test_two_step_adjoint_equals_one_update_per_launch(k, steps):
+    """The adjoint loop (receivers injected, sources sampled, time reversed):
+    bitwise equal with two updates per launch and with one, and within the
+    record bar of the oracle's adjoint."""
+    from _harness import noise
+    P = make_problem((36, 19, 117), 8, k, steps, seed=290 + k + steps, nrec=40)
+    src, _ = _scatter_sources(P, 16, seed=30 + k)
+    rec = np.vstack([P.rec_xyz, src[:6]])
+    y = noise(P.nt, rec.shape[0], P.dt, 15.0, 7 + steps).astype(np.float32)
+    prop = P.propagator()
+    x2, n2 = _adjoint(P, True, prop, rec, y, src)
+    x1, n1 = _adjoint(P, False, prop, rec, y, src)
+    assert (n2, n1) == (steps // 2, 0)
+    assert torch.equal(x2, x1), float((x2 - x1).abs().max())
+    assert float(x1.abs().max()) > 0
+    if steps == 10:
+        import oracle
+        ref = oracle.adjoint(P.grid(), P.m64(), P.eta(), P.dt, P.nt, P.pts(rec), y.astype(np.float64),
+                             P.pts(src))
+        check_record(x2.cpu().numpy(), ref, label="adjoint, two updates per launch, order %d" % k)
