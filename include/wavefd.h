@@ -188,7 +188,7 @@ wf_status wf_graph_enable(int on);
  * updates instead of 32 (the update is bound by memory traffic, Section
  * "Performance"), at the price of recomputing u^{n+1} on a margin around
  * every tile. 0: one update per launch; 1 (the default): two where that was
- * measured faster (space order 4 on grids of at least 8e7 nodes); 2: two
+ * measured faster (space order 4 on grids of at least 9e7 nodes); 2: two
  * wherever compiled (orders 4 and 8). The environment's WAVEFD_TWO_STEP=0 or
  * =2 sets the mode at start-up. Records, saved fields and the final fields
  * are the same bits in every mode. Such a loop keeps a second pair of

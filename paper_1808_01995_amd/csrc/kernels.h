@@ -148,7 +148,8 @@ hipError_t launch_team(const TeamArgs& a, int ndim, int half, int nwg, hipStream
 // Two plain updates in one pass (3D, half orders 2 and 4): u^{n+1} and
 // u^{n+2} from u^n and u^{n-1}, each node with the arithmetic of the
 // single-update kernel (so the fields are the same bits). A block owns an
-// inner (y, z) tile of by x 4(kStep2Cols - 2 hz) nodes (hz = ceil(M / 4)) and
+// inner (y, z) tile of by x 4(kStep2Cols - 2 hz) nodes (hz = ceil(M / 4);
+// by = 20 at half order 2, 16 at 4) and
 // an x chunk; it computes u^{n+1} on the tile extended by M rows and 4 hz
 // nodes on each side and on M planes beyond either end of its chunk, keeps it
 // in registers and LDS, and from it u^{n+2} on the inner tile. Reads u^n,

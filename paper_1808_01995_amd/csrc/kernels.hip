@@ -1572,29 +1572,33 @@ hipError_t launch_step(const StepParams& p, int ndim, int half, int mode, hipStr
     return hipLaunchKernel(fn, dim3(grid), dim3(ts.bz * ts.by), args, 0, s);
 }
 
-// Two-update kernel: 16 inner rows (20 or 24 extended rows of 32 float4
-// columns: 640 or 768 threads), one block per CU (its two rings and the LDS
-// reads in flight hold about 160 VGPRs); the u^n ring prefetches one plane.
-// Per order, as measured at 592^3 (us per launch of two updates): order 4
-// with u^{n-1} and kap cached (neighbouring blocks re-read the rows their
-// extended tiles share: 1129 against 1195 streamed), order 8 also reloading
-// kap for the second update instead of keeping a ring of it (1424 against
-// 1525: the ring spilled); a deeper prefetch spilled more and was slower.
-constexpr int kStep2By = 16;
+// Two-update kernel: 24 extended rows of 32 float4 columns (768 threads),
+// i.e. 20 inner rows at order 4 and 16 at order 8, one block per CU (its two
+// rings and the LDS reads in flight hold about 165 VGPRs); the u^n ring
+// prefetches one plane. Per order, as measured at 592^3 (us per launch of
+// two updates): order 4 with u^{n-1} and kap cached (neighbouring blocks
+// re-read the rows their extended tiles share: 1129 against 1195 streamed,
+// 16 inner rows) and 20 inner rows (1076; 16 rows recompute a larger share);
+// order 8 also reloading kap for the second update instead of keeping a ring
+// of it (1424 against 1525: the ring spilled), 16 inner rows (12: 1473); a
+// deeper prefetch spilled more and was slower.
+constexpr int step2_rows(int half) { return half == 2 ? 20 : 16; }
 // Measured against two single-update launches (us per update, constant
-// velocity, 40 updates): order 4 gains 1.13-1.16 x from 464^3 (1.0e8 nodes)
-// to 592^3, breaks even at 400^3 and loses at 272^3 and 336^3 (0.90-0.94 x),
-// where the single-update kernel finds much of its traffic in the Infinity
-// Cache; order 8 is bound by instruction issue (every tile recomputes u^{n+1}
-// on a margin of M rows and 4 nodes) and loses at every size from 208^3 to
-// 592^3 (0.76-0.93 x).
-constexpr int64_t kStep2MinNodes = 80000000;
+// velocity, 40 updates): order 4 gains 1.13-1.21 x from 464^3 (1.0e8 nodes)
+// to 592^3; below that the result swings with how the 120-node z tiles and
+// 20-row y tiles fill the grid and how many rounds of blocks the chunking
+// needs (400^3 1.07 x, 432^3 0.99 x, 368^3 0.73 x with a last z tile of 8
+// nodes, 272^3 to 336^3 0.89-0.96 x where the single-update kernel also
+// finds much of its traffic in the Infinity Cache); order 8 is bound by
+// instruction issue (every tile recomputes u^{n+1} on a margin of M rows and
+// 4 nodes) and loses at every size from 208^3 to 592^3 (0.76-0.93 x).
+constexpr int64_t kStep2MinNodes = 90000000;
 
 namespace {
 const void* step2_fn(int half) {
     switch (half) {
-        case 2: return reinterpret_cast<const void*>(&k_step2<2, kStep2By, 1, 1, false, false>);
-        case 4: return reinterpret_cast<const void*>(&k_step2<4, kStep2By, 1, 1, true, false>);
+        case 2: return reinterpret_cast<const void*>(&k_step2<2, step2_rows(2), 1, 1, false, false>);
+        case 4: return reinterpret_cast<const void*>(&k_step2<4, step2_rows(4), 1, 1, true, false>);
         default: return nullptr;
     }
 }
@@ -1610,7 +1614,7 @@ int step2_threads(int half, int by) { return (by + 2 * half) * kStep2Cols; }
 void step2_plan(Step2Params& p, int half, int cx_request) {
     static std::mutex mu;
     static int cap_cache[kMaxHalf + 1] = {};
-    p.by = kStep2By;
+    p.by = step2_rows(half);
     const int tz = 4 * (kStep2Cols - 2 * step2_ext_cols(half));
     p.ntz = (p.nz + tz - 1) / tz;
     p.nty = (p.ny + p.by - 1) / p.by;
@@ -1661,7 +1665,7 @@ void step2_plan(Step2Params& p, int half, int cx_request) {
 hipError_t launch_step2(const Step2Params& p, int half, hipStream_t s) {
     if (p.nblocks <= 0) return hipSuccess;
     const void* fn = step2_fn(half);
-    if (!fn || p.by != kStep2By) return hipErrorInvalidValue;
+    if (!fn || p.by != step2_rows(half)) return hipErrorInvalidValue;
     const int grid = ((p.nblocks + 7) / 8) * 8;
     void* args[] = {const_cast<Step2Params*>(&p)};
     return hipLaunchKernel(fn, dim3(grid), dim3(step2_threads(half, p.by)), args, 0, s);
