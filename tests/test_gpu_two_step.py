@@ -149,3 +149,52 @@ def test_two_step_adjoint_equals_one_update_per_launch(k, steps):
         ref = oracle.adjoint(P.grid(), P.m64(), P.eta(), P.dt, P.nt, P.pts(rec), y.astype(np.float64),
                              P.pts(src))
         check_record(x2.cpu().numpy(), ref, label="adjoint, two updates per launch, order %d" % k)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_two_step_loops_replay_from_graphs(k):
+    """With capture on, a forward and an adjoint loop of two-update launches
+    are captured on their second call and replayed after; every replay,
+    with other eager work on the model in between, equals the eager
+    one-update-per-launch run bit for bit."""
+    from _harness import noise
+    from paper_1808_01995_amd import _abi
+    P = make_problem((30, 20, 118), 6, k, 13, seed=310 + k, nrec=30)
+    prop = P.propagator()
+    q = torch.from_numpy(P.q32).cuda()
+    y = torch.from_numpy(noise(P.nt, P.rec_xyz.shape[0], P.dt, 15.0, 3).astype(np.float32)).cuda()
+    rec = torch.empty((P.nt, P.rec_xyz.shape[0]), dtype=torch.float32, device="cuda")
+    xs = torch.empty((P.nt, P.src_xyz.shape[0]), dtype=torch.float32, device="cuda")
+
+    def fwd():
+        _abi.wf_forward(prop.handle, P.dt, P.nt, P.src_xyz, q, P.rec_xyz, rec)
+        return rec.clone()
+
+    def adj():
+        _abi.wf_adjoint(prop.handle, P.dt, P.nt, P.rec_xyz, y, P.src_xyz, xs)
+        return xs.clone()
+
+    _abi.wf_two_step_enable(0)
+    ref_f, ref_a = fwd(), adj()
+    torch.cuda.synchronize()
+    _abi.wf_two_step_enable(2)
+    _abi.wf_graph_enable(True)
+    try:
+        # a first round sizes the model's increment buffers for both loops (a
+        # grown buffer changes a loop's signature; the adjoint's receivers need
+        # the larger ones, so it goes first) and runs eagerly
+        a0 = adj()
+        outs = [(fwd(), a0)]
+        torch.cuda.synchronize()
+        g0 = _abi.wf_model_graph_launches(prop.handle)
+        for _ in range(3):
+            outs.append((fwd(), adj()))
+            torch.cuda.synchronize()
+        launched = _abi.wf_model_graph_launches(prop.handle) - g0
+    finally:
+        _abi.wf_graph_enable(False)
+        _abi.wf_two_step_enable(1)
+    assert launched == 6, launched   # per loop: capture and launch, then two replays
+    for f, a in outs:
+        assert torch.equal(f, ref_f)
+        assert torch.equal(a, ref_a)
