@@ -198,3 +198,24 @@ def test_two_step_loops_replay_from_graphs(k):
     for f, a in outs:
         assert torch.equal(f, ref_f)
         assert torch.equal(a, ref_a)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("shape,nbl", [((3, 5, 7), 2),        # fewer planes, rows and columns than one tile
+                                       ((6, 4, 112), 4),      # 120 z nodes: exactly one z tile
+                                       ((12, 12, 232), 4),    # 240 z nodes: exactly two; 20 y rows
+                                       ((2, 2, 2), 2)])       # 6 x 6 x 6 nodes
+def test_two_step_small_and_exact_tile_grids(k, shape, nbl):
+    """Degenerate and exact-fit shapes: grids smaller than one tile in every
+    axis, z extents that fill whole 120-node tiles, y extents that fill whole
+    tiles; sources on the first and last nodes. Records bitwise equal to one
+    update per launch, for an odd and an even number of updates."""
+    for steps in (5, 6):
+        P = make_problem(shape, nbl, k, steps, seed=330 + k + steps, nrec=12)
+        src, q = _scatter_sources(P, 6, seed=steps)
+        rec = np.vstack([P.rec_xyz, src])
+        prop = P.propagator()
+        d2, _, n2 = _forward(P, True, prop=prop, src=src, q=q, rec=rec)
+        d1, _, _ = _forward(P, False, prop=prop, src=src, q=q, rec=rec)
+        assert n2 == steps // 2
+        assert torch.equal(d2, d1), (shape, steps, float((d2 - d1).abs().max()))
