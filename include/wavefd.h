@@ -195,8 +195,8 @@ wf_status wf_graph_enable(int on);
  * wavefields in the model (counted by wf_model_bytes, freed by
  * wf_model_trim); calls made through the serving engine or the
  * allocation-free entry point keep one update per launch, and so does a loop
- * whose sources crowd a block beyond what it can stage. Other modes:
- * WF_E_ARG. */
+ * whose sources crowd a block beyond what it can stage or for which those two
+ * fields cannot be allocated. Other modes: WF_E_ARG. */
 wf_status wf_two_step_enable(int mode);
 
 /* Free the model and everything it holds. Synchronises its device work. */

@@ -376,7 +376,17 @@ struct TwoStep {
             p2.smp_n = smp.npts;
             p2.smp_per = (int)(((int64_t)smp.npts + p2.nblocks - 1) / p2.nblocks);
         }
-        return md.ensure_u2(s);
+        // without room for the second field pair the loop keeps one update
+        // per launch (the same results), rather than failing
+        const wf_status st = md.ensure_u2(s);
+        if (st == WF_E_NOMEM) {
+            clear_error();
+            md.d_u2[0].reset();
+            md.d_u2[1].reset();
+            on = false;
+            return WF_OK;
+        }
+        return st;
     }
     void key(std::vector<int64_t>& v, const Model& md) const {
         v.push_back(on ? 1 : 0);
