@@ -144,8 +144,11 @@ def graph_c1(torch, shots=20):
     def shot():
         prop.forward(dt, c.nt, c.src, q, c.rec, rec_out=rec)
 
-    res = {"workload": "C1: 141^2 computational, order 4, %d updates, 101 receivers" % c.steps}
-    for mode in ("eager", "graph"):
+    res = {"workload": "C1: 141^2 computational, order 4, %d updates, 101 receivers" % c.steps,
+           "note": "eager and graph: two updates per launch (the default for 2D order 4); "
+                   "eager_one_update_per_launch: the same shots with one"}
+    for mode, two in (("eager", 1), ("graph", 1), ("eager_one_update_per_launch", 0)):
+        _abi.wf_two_step_enable(two)
         _abi.wf_graph_enable(mode == "graph")
         shot()
         shot()     # graph mode: captured here
@@ -155,6 +158,7 @@ def graph_c1(torch, shots=20):
                      "gpts": round(prop.npoints * c.steps / el / 1e9, 3),
                      "graph_launches": _abi.wf_model_graph_launches(prop.handle) - g0}
     _abi.wf_graph_enable(False)
+    _abi.wf_two_step_enable(1)
     res["graph_speedup"] = round(res["eager"]["ms_per_shot"] / res["graph"]["ms_per_shot"], 2)
     prop.close()
     log("c1: %s" % res)
@@ -203,7 +207,9 @@ def c1_batch(torch, counts=(1, 8, 32, 256), steps=500):
 def large_2d(torch, n=8192, orders=(4, 8, 12), steps=300):
     """Large 2D grids: n^2 physical + 40-node layer, v = 2 km/s, one source,
     256 receivers at 20 m; GPts/s and the step kernel's algorithmic bandwidth
-    (HIP events around every 4th launch)."""
+    per update (the shot's run of step launches timed by one pair of HIP
+    events). Where the default runs two updates per launch the same shot
+    also runs with one, for comparison."""
     from paper_1808_01995_amd import Propagator, _abi
     from synthetic import ricker
     res = []
@@ -217,19 +223,32 @@ def large_2d(torch, n=8192, orders=(4, 8, 12), steps=300):
         rec = np.stack([np.linspace(0, ext, 256), np.full(256, 20.0)], 1)
         q = torch.from_numpy(ricker(nt, dt, 10.0)[:, None].astype(np.float32)).cuda()
         out = torch.empty((nt, 256), device="cuda")
-        prop.forward(dt, 21, src, q[:21].contiguous(), rec, rec_out=out[:21])
-        _abi.wf_profile_read(0, reset=True)
-        _abi.wf_profile_enable(4)
-        el, _ = _timed(torch, lambda: prop.forward(dt, nt, src, q, rec, rec_out=out))
-        _abi.wf_profile_enable(False)
-        ms, k = _abi.wf_profile_read(0, reset=True)
-        us = ms / max(k, 1) * 1e3
-        gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
-        res.append({"space_order": so, "gpts": round(prop.npoints * steps / el / 1e9, 1),
-                    "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs),
-                    "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3)})
+        for mode in (1, 0):
+            _abi.wf_two_step_enable(mode)
+            prop.forward(dt, 21, src, q[:21].contiguous(), rec, rec_out=out[:21])
+            _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN, reset=True)
+            _abi.wf_profile_runs_enable(True)
+            el, _ = _timed(torch, lambda: prop.forward(dt, nt, src, q, rec, rec_out=out))
+            _abi.wf_profile_runs_enable(False)
+            ms1, n1 = _abi.wf_profile_read(_abi.WF_KERNEL_STEP_RUN)
+            ms2, n2 = _abi.wf_profile_read(_abi.WF_KERNEL_STEP2_RUN, reset=True)
+            us = (ms1 + ms2) / max(n1 + 2 * n2, 1) * 1e3
+            gbs = BYTES_PER_POINT * prop.npoints / (us * 1e-6) / 1e9
+            r = {"space_order": so, "gpts": round(prop.npoints * steps / el / 1e9, 1),
+                 "updates_per_launch": 2 if n2 else 1,
+                 "step_kernel_us": round(us, 1), "algorithmic_GBs": round(gbs),
+                 "frac_8TBs": round(gbs / PEAK_HBM_GBS, 3)}
+            if n2:
+                two_us = ms2 / n2 * 1e3
+                r.update({"step_kernel_us_note": "per update; 16 B per node per update",
+                          "two_update_launch_us": round(two_us, 1),
+                          "two_update_frac_8TBs": round(20.0 * prop.npoints / (two_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 3)})
+            res.append(r)
+            log("2d %d so%d: %s" % (n, so, res[-1]))
+            if not n2:
+                break
+        _abi.wf_two_step_enable(1)
         prop.close()
-        log("2d %d so%d: %s" % (n, so, res[-1]))
     return {"workload": "%d^2 physical (%d^2 computational), %d updates" % (n, n + 80, steps), "orders": res}
 
 

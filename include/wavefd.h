@@ -182,21 +182,22 @@ wf_status wf_validate_enable(int on);
 wf_status wf_graph_enable(int on);
 
 /* Process-wide mode for running the time loops of wf_forward and wf_adjoint
- * on 3D models of space order 4 or 8 two updates (eq. eulerfwd with the damping of eq.
- * fdWE-abc, applied twice) per kernel launch: the launch reads u^n, u^{n-1}
- * and kappa once and writes u^{n+1} and u^{n+2}, 20 bytes per node for two
- * updates instead of 32 (the update is bound by memory traffic, Section
- * "Performance"), at the price of recomputing u^{n+1} on a margin around
- * every tile. 0: one update per launch; 1 (the default): two where that was
- * measured faster (space order 4 on grids of at least 9e7 nodes); 2: two
- * wherever compiled (orders 4 and 8). The environment's WAVEFD_TWO_STEP=0 or
- * =2 sets the mode at start-up. Records, saved fields and the final fields
- * are the same bits in every mode. Such a loop keeps a second pair of
- * wavefields in the model (counted by wf_model_bytes, freed by
- * wf_model_trim); calls made through the serving engine or the
- * allocation-free entry point keep one update per launch, and so does a loop
- * whose sources crowd a block beyond what it can stage or for which those two
- * fields cannot be allocated. Other modes: WF_E_ARG. */
+ * on models of space order 4 or 8 two updates (eq. eulerfwd with the damping
+ * of eq. fdWE-abc, applied twice) per kernel launch: the launch reads u^n,
+ * u^{n-1} and kappa once and writes u^{n+1} and u^{n+2}, 20 bytes per node
+ * for two updates instead of 32 (the update is bound by memory traffic,
+ * Section "Performance"), at the price of recomputing u^{n+1} on a margin
+ * around every tile (M rows in 3D, 4 nodes along z in 2D and 3D). 0: one
+ * update per launch; 1 (the default): two where that was measured faster
+ * (2D order 4 at every size, 2D order 8 from 5e7 nodes, 3D order 4 from 9e7
+ * nodes); 2: two wherever compiled (orders 4 and 8, 2D and 3D). The
+ * environment's WAVEFD_TWO_STEP=0 or =2 sets the mode at start-up. Records,
+ * saved fields and the final fields are the same bits in every mode. Such a
+ * loop keeps a second pair of wavefields in the model (counted by
+ * wf_model_bytes, freed by wf_model_trim); calls made through the serving
+ * engine or the allocation-free entry point keep one update per launch, and
+ * so does a loop whose sources crowd a block beyond what it can stage or for
+ * which those two fields cannot be allocated. Other modes: WF_E_ARG. */
 wf_status wf_two_step_enable(int mode);
 
 /* Free the model and everything it holds. Synchronises its device work. */

@@ -255,8 +255,9 @@ def wf_graph_enable(on: bool):
 
 
 def wf_two_step_enable(mode: int):
-    """Two updates per launch in 3D forward loops: 0 off, 1 where measured
-    faster (the default), 2 for every compiled order (4 and 8)."""
+    """Two updates per launch in forward and adjoint loops: 0 off, 1 where
+    measured faster (the default), 2 for every compiled order (4 and 8, 2D
+    and 3D)."""
     _check(lib.wf_two_step_enable(int(mode)))
 
 

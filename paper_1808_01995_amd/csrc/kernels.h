@@ -145,19 +145,22 @@ struct TeamArgs {
 bool team_fits(int64_t nx, int64_t ny, int64_t nz);
 hipError_t launch_team(const TeamArgs& a, int ndim, int half, int nwg, hipStream_t s);
 
-// Two plain updates in one pass (3D, half orders 2 and 4): u^{n+1} and
-// u^{n+2} from u^n and u^{n-1}, each node with the arithmetic of the
+// Two plain updates in one pass (2D and 3D, half orders 2 and 4): u^{n+1}
+// and u^{n+2} from u^n and u^{n-1}, each node with the arithmetic of the
 // single-update kernel (so the fields are the same bits). A block owns an
-// inner (y, z) tile of by x 4(kStep2Cols - 2 hz) nodes (hz = ceil(M / 4);
-// by = 20 at half order 2, 16 at 4) and
-// an x chunk; it computes u^{n+1} on the tile extended by M rows and 4 hz
-// nodes on each side and on M planes beyond either end of its chunk, keeps it
-// in registers and LDS, and from it u^{n+2} on the inner tile. Reads u^n,
+// inner (y, z) tile of by x 4(step2_cols - 2 hz) nodes (hz = ceil(M / 4); in
+// 3D by = 20 at half order 2 and 16 at 4, in 2D one row) and an x chunk; it
+// computes u^{n+1} on the tile extended by M rows (3D) and 4 hz nodes on
+// each side and on M planes beyond either end of its chunk, keeps it in
+// registers and LDS, and from it u^{n+2} on the inner tile. Reads u^n,
 // u^{n-1} and kap, writes u^{n+1} and u^{n+2} (20 bytes per node for two
 // updates). None of the four fields may alias another: neighbouring blocks
 // read cur and old where this block writes.
-constexpr int kStep2Cols = 32;    // float4 columns per row of the extended tile
-constexpr int kInjCap2x = 512;    // injection entries per block and update
+// float4 columns per row of the extended tile, and injection entries per
+// block and update (a 2D block is one row and stages fewer, so that several
+// blocks fit a CU's LDS)
+__host__ __device__ constexpr int step2_cols(bool d3) { return d3 ? 32 : 128; }
+__host__ __device__ constexpr int step2_inj_cap(bool d3) { return d3 ? 512 : 128; }
 struct Step2Params {
     const float* cur;    // u^n
     const float* old;    // u^{n-1}
@@ -197,12 +200,13 @@ bool step2_supported(int ndim, int half);
 bool step2_preferred(int ndim, int half, int64_t nodes);
 // Plan tiles and chunks from the grid in p (nx, ny, nz set); cx_request > 0
 // forces the chunk length.
-void step2_plan(Step2Params& p, int half, int cx_request);
-// Threads per block of the planned launch, and the extension in rows and
-// float4 columns on each side of the inner tile.
-int step2_threads(int half, int by);
+void step2_plan(Step2Params& p, int ndim, int half, int cx_request);
+// Threads per block of the planned launch, and the extension in float4
+// columns on each side of the inner tile (the extension in rows is half in
+// 3D, none in 2D).
+int step2_threads(int ndim, int half, int by);
 int step2_ext_cols(int half);
-hipError_t launch_step2(const Step2Params& p, int half, hipStream_t s);
+hipError_t launch_step2(const Step2Params& p, int ndim, int half, hipStream_t s);
 
 // Tile shapes (threads along z carry 4 points each).
 struct TileShape {

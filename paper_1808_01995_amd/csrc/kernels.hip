@@ -484,9 +484,9 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 // ---------------------------------------------------------------------------
 // Two plain updates per pass (3D): temporal blocking over overlapping tiles.
 //
-// Block: EY = BY + 2M rows of kStep2Cols threads, one float4 column each,
+// Block: EY = BY + 2M rows (3D; one row in 2D) of BZE threads, one float4 column each,
 // over the extended tile; the inner tile is rows [M, M + BY) and columns
-// [HZ, kStep2Cols - HZ). For its chunk [xb, xe) the block walks planes
+// [HZ, BZE - HZ). For its chunk [xb, xe) the block walks planes
 // x = xb - M .. xe + M - 1: every thread forms u^{n+1}(x) of its column from
 // a register ring of u^n planes (x taps) and an LDS plane of u^n that holds
 // the extended tile plus a frame of M rows and P nodes (y and z taps), and
@@ -502,16 +502,16 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 // kap; KR: the second update reloads kap (else a register ring keeps M + 1
 // planes of it, LA = 1 only); NT: u^{n-1} and kap streamed non-temporal
 // (else cached, so that the overlapping rows of neighbouring blocks can hit).
-template <int M, int BY, int PF, int LA, bool KR, bool NTS>
+template <bool D3, int M, int BY, int BZE, int PF, int LA, bool KR, bool NTS>
 __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx) {
     constexpr int HZ = (M + 3) / 4;
     constexpr int P = 4 * HZ;              // z extension and z frame (nodes)
-    constexpr int BZE = kStep2Cols;
     constexpr int TZ = 4 * (BZE - 2 * HZ); // inner tile along z
-    constexpr int EY = BY + 2 * M;         // rows of the extended tile
+    constexpr int MY = D3 ? M : 0;         // y extension and y frame (rows)
+    constexpr int EY = BY + 2 * MY;        // rows of the extended tile
     constexpr int NT = EY * BZE;
     constexpr int LWA = 4 * BZE + 2 * P;   // u^n plane: row width with the z frame
-    constexpr int LBA = (EY + 2 * M) * LWA;
+    constexpr int LBA = (EY + 2 * MY) * LWA;
     constexpr int LWU = 4 * BZE;           // u^{n+1} plane: the extended tile
     constexpr int LBU = EY * LWU;
     constexpr int NQ = 2 * M + 1 + PF;     // u^n ring; the u^{n+1} ring has the same length
@@ -520,13 +520,14 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
     static_assert(NQ % KQ == 0 && NQ % HL == 0 && NQ % LA == 0, "ring lengths must divide the unrolled loop");
     static_assert(KR || LA == 1, "the kap ring takes the next plane only");
     auto lds_ = [](const float* q) { return NTS ? ld4s(q) : ld4(q); };
-    constexpr int NFY = 2 * M * BZE;       // frame rows above and below (float4 loads)
+    constexpr int NFY = 2 * MY * BZE;      // frame rows above and below (float4 loads)
     constexpr int NFZ = 2 * EY * HZ;       // frame columns left and right
     constexpr int JF = (NFY + NFZ + NT - 1) / NT;
     __shared__ __attribute__((aligned(16))) float la[2 * LBA];
     __shared__ __attribute__((aligned(16))) float lu[2 * LBU];
-    __shared__ int inj_xl[2][kInjCap2x];
-    __shared__ float4 inj_vl[2][kInjCap2x];
+    constexpr int ICAP = step2_inj_cap(D3);
+    __shared__ int inj_xl[2][ICAP];
+    __shared__ float4 inj_vl[2][ICAP];
 
     const int r = xcd_remap(bidx, p.nblocks);
     if (r >= p.nblocks) return;
@@ -539,9 +540,9 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
     const int tid = threadIdx.x;
     const int lz = tid % BZE, ly = tid / BZE;
     const int z0 = itz * TZ, y0 = ity * BY;
-    const int y = y0 - M + ly, z = z0 - P + 4 * lz;
+    const int y = y0 - MY + ly, z = z0 - P + 4 * lz;
     const bool ing = y >= 0 && y < p.ny && z >= 0 && z < p.nz;
-    const bool inner = ly >= M && ly < M + BY && lz >= HZ && lz < BZE - HZ;
+    const bool inner = ly >= MY && ly < MY + BY && lz >= HZ && lz < BZE - HZ;
     const int xb = ich * p.cx;
     const int xe = min(xb + p.cx, p.nx);
     const int xs = xb - M, xend = xe + M;
@@ -561,8 +562,8 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
         int gy = -1, gz = -1, l = -1;
         if (i < NFY) {
             const int rr = i / BZE, cz = i - rr * BZE;
-            const int lr = rr < M ? rr : rr + EY;
-            gy = y0 - 2 * M + lr;
+            const int lr = rr < MY ? rr : rr + EY;
+            gy = y0 - 2 * MY + lr;
             gz = z0 - P + 4 * cz;
             l = lr * LWA + P + 4 * cz;
         } else if (i < NFY + NFZ) {
@@ -570,9 +571,9 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
             const int rr = k / (2 * HZ), kk = k - rr * (2 * HZ);
             const int side = kk / HZ, q = kk - side * HZ;
             const int lc = side ? (P + 4 * BZE + 4 * q) : 4 * q;
-            gy = y0 - M + rr;
+            gy = y0 - MY + rr;
             gz = z0 - 2 * P + lc;
-            l = (rr + M) * LWA + lc;
+            l = (rr + MY) * LWA + lc;
         }
         if (l >= 0) {
             hf_l[j] = l;
@@ -584,7 +585,7 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
     float eyz[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        eyz[i] = (ing && z + i < p.nz) ? (p.etay[y] + p.etaz[z + i]) : 0.0f;
+        eyz[i] = (ing && z + i < p.nz) ? ((D3 ? p.etay[y] : 0.0f) + p.etaz[z + i]) : 0.0f;
 
     // injection entries of both updates -> LDS; each thread's next entry of
     // each list in registers (as in step_body)
@@ -634,7 +635,7 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
     // this block's share of the receivers, from both fields it only reads
     // (k_sample's corner order)
     if (p.smp_cur || p.smp_old) {
-        constexpr int KS = 8;
+        constexpr int KS = D3 ? 8 : 4;   // corners of a cell
         const int s0 = r * p.smp_per, s1 = min(s0 + p.smp_per, p.smp_n);
         for (int i = s0 + tid; i < s1; i += NT) {
             int64_t so[KS];
@@ -682,7 +683,7 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
                 const float4 c = ring[(ph + M) % NQ];
                 float* A = la + (x & 1) * LBA;
                 float* U = lu + (x & 1) * LBU;
-                float* arow = A + (ly + M) * LWA;
+                float* arow = A + (ly + MY) * LWA;
                 float* urow = U + ly * LWU;
                 st4(arow + P + 4 * lz, ing ? c : zero4());
 #pragma unroll
@@ -705,7 +706,7 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
                         lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
                     }
 #pragma unroll
-                    for (int j = 1; j <= M; ++j) {
+                    for (int j = 1; j <= MY; ++j) {
                         const float4 a = ld4(arow - j * LWA + P + 4 * lz);
                         const float4 b = ld4(arow + j * LWA + P + 4 * lz);
                         lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
@@ -765,7 +766,7 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
                         lap[3] = fmaf(p.wx[j], a.w + b.w, lap[3]);
                     }
 #pragma unroll
-                    for (int j = 1; j <= M; ++j) {
+                    for (int j = 1; j <= MY; ++j) {
                         const float4 a = ld4(urow - j * LWU + 4 * lz);
                         const float4 b = ld4(urow + j * LWU + 4 * lz);
                         lap[0] = fmaf(p.wy[j], a.x + b.x, lap[0]);
@@ -819,9 +820,9 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
     }
 }
 
-template <int M, int BY, int PF, int LA, bool KR, bool NTS>
-__global__ void __launch_bounds__((BY + 2 * M) * kStep2Cols, 1) k_step2(const Step2Params p) {
-    step2_body<M, BY, PF, LA, KR, NTS>(p, (int)blockIdx.x);
+template <bool D3, int M, int BY, int BZE, int PF, int LA, bool KR, bool NTS>
+__global__ void __launch_bounds__((BY + 2 * (D3 ? M : 0)) * BZE, D3 ? 1 : 3) k_step2(const Step2Params p) {
+    step2_body<D3, M, BY, BZE, PF, LA, KR, NTS>(p, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1594,46 +1595,74 @@ constexpr int step2_rows(int half) { return half == 2 ? 20 : 16; }
 // 4 nodes) and loses at every size from 208^3 to 592^3 (0.76-0.93 x).
 constexpr int64_t kStep2MinNodes = 90000000;
 
+// 2D rows: 128 float4 columns (504 inner nodes along z), two waves per
+// block and several blocks per CU; the margin is 4 z nodes per side, so
+// the recomputed work is under 2 %. Measured against one update per launch
+// (constant velocity, nbl 20-40): order 4 gains at every size from 141^2
+// (3.35 against 3.99 us per update: half the launches) to 8272^2 (1.04-1.38
+// x); order 8 loses from 141^2 to 1448^2 (0.78-0.86 x: the stencil's
+// issue time per launch exceeds the launch it saves), breaks even at 2896^2
+// and 5792^2 (1.02, 0.97 x) and gains 1.30 x at 8272^2 (6.8e7 nodes), where
+// a single-update launch no longer finds its fields in the Infinity Cache.
+constexpr int64_t kStep2MinNodes2dOrder8 = 50000000;
+
 namespace {
-const void* step2_fn(int half) {
-    switch (half) {
-        case 2: return reinterpret_cast<const void*>(&k_step2<2, step2_rows(2), 1, 1, false, false>);
-        case 4: return reinterpret_cast<const void*>(&k_step2<4, step2_rows(4), 1, 1, true, false>);
-        default: return nullptr;
+const void* step2_fn(int ndim, int half) {
+    constexpr int C3 = step2_cols(true), C2 = step2_cols(false);
+    if (ndim == 3) {
+        switch (half) {
+            case 2: return reinterpret_cast<const void*>(&k_step2<true, 2, step2_rows(2), C3, 1, 1, false, false>);
+            case 4: return reinterpret_cast<const void*>(&k_step2<true, 4, step2_rows(4), C3, 1, 1, true, false>);
+            default: return nullptr;
+        }
     }
+    if (ndim == 2) {
+        switch (half) {
+            case 2: return reinterpret_cast<const void*>(&k_step2<false, 2, 1, C2, 1, 1, false, false>);
+            case 4: return reinterpret_cast<const void*>(&k_step2<false, 4, 1, C2, 1, 1, true, false>);
+            default: return nullptr;
+        }
+    }
+    return nullptr;
 }
+int step2_by(int ndim, int half) { return ndim == 3 ? step2_rows(half) : 1; }
 }  // namespace
 
-bool step2_supported(int ndim, int half) { return ndim == 3 && step2_fn(half) != nullptr; }
+bool step2_supported(int ndim, int half) { return step2_fn(ndim, half) != nullptr; }
 bool step2_preferred(int ndim, int half, int64_t nodes) {
-    return step2_supported(ndim, half) && half == 2 && nodes >= kStep2MinNodes;
+    if (!step2_supported(ndim, half)) return false;
+    if (ndim == 2) return half == 2 || nodes >= kStep2MinNodes2dOrder8;
+    return half == 2 && nodes >= kStep2MinNodes;
 }
 int step2_ext_cols(int half) { return (half + 3) / 4; }
-int step2_threads(int half, int by) { return (by + 2 * half) * kStep2Cols; }
+int step2_threads(int ndim, int half, int by) {
+    return (by + (ndim == 3 ? 2 * half : 0)) * step2_cols(ndim == 3);
+}
 
-void step2_plan(Step2Params& p, int half, int cx_request) {
+void step2_plan(Step2Params& p, int ndim, int half, int cx_request) {
     static std::mutex mu;
-    static int cap_cache[kMaxHalf + 1] = {};
-    p.by = step2_rows(half);
-    const int tz = 4 * (kStep2Cols - 2 * step2_ext_cols(half));
+    static int cap_cache[2][kMaxHalf + 1] = {};
+    p.by = step2_by(ndim, half);
+    const int tz = 4 * (step2_cols(ndim == 3) - 2 * step2_ext_cols(half));
     p.ntz = (p.nz + tz - 1) / tz;
     p.nty = (p.ny + p.by - 1) / p.by;
     const int64_t tiles = (int64_t)p.ntz * p.nty;
     int cap = 0;
     {
         std::lock_guard<std::mutex> lk(mu);
-        if (cap_cache[half] <= 0) {
+        int& cc = cap_cache[ndim == 3][half];
+        if (cc <= 0) {
             int dev = 0, cus = 0, per = 0;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 cus = 256;
-            const void* fn = step2_fn(half);
-            if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, step2_threads(half, p.by), 0) !=
+            const void* fn = step2_fn(ndim, half);
+            if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, step2_threads(ndim, half, p.by), 0) !=
                            hipSuccess || per < 1)
                 per = 1;
-            cap_cache[half] = per * cus;
+            cc = per * cus;
         }
-        cap = cap_cache[half];
+        cap = cc;
     }
     int cx = cx_request;
     if (cx <= 0) {
@@ -1662,13 +1691,13 @@ void step2_plan(Step2Params& p, int half, int cx_request) {
     p.nblocks = (int)(tiles * p.nchunks);
 }
 
-hipError_t launch_step2(const Step2Params& p, int half, hipStream_t s) {
+hipError_t launch_step2(const Step2Params& p, int ndim, int half, hipStream_t s) {
     if (p.nblocks <= 0) return hipSuccess;
-    const void* fn = step2_fn(half);
-    if (!fn || p.by != step2_rows(half)) return hipErrorInvalidValue;
+    const void* fn = step2_fn(ndim, half);
+    if (!fn || p.by != step2_by(ndim, half)) return hipErrorInvalidValue;
     const int grid = ((p.nblocks + 7) / 8) * 8;
     void* args[] = {const_cast<Step2Params*>(&p)};
-    return hipLaunchKernel(fn, dim3(grid), dim3(step2_threads(half, p.by)), args, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(step2_threads(ndim, half, p.by)), args, 0, s);
 }
 
 template <int M>

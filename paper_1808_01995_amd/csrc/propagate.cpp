@@ -343,27 +343,27 @@ struct TwoStep {
         std::copy(p.wy, p.wy + kMaxHalf + 1, p2.wy);
         std::copy(p.wz, p.wz + kMaxHalf + 1, p2.wz);
         p2.inv2dt = p.inv2dt;
-        step2_plan(p2, md.half, 0);
+        step2_plan(p2, L.ndim, md.half, 0);
         if (pts.nnodes > 0) {
-            const int M = md.half, hz = step2_ext_cols(M);
+            const int M = md.half, hz = step2_ext_cols(M), my = L.ndim == 3 ? M : 0;
             InjGeom g;
-            g.tz = 4 * (kStep2Cols - 2 * hz);
+            g.tz = 4 * (step2_cols(L.ndim == 3) - 2 * hz);
             g.ty = p2.by;
-            g.bz = kStep2Cols;
-            g.nt = step2_threads(M, p2.by);
+            g.bz = step2_cols(L.ndim == 3);
+            g.nt = step2_threads(L.ndim, M, p2.by);
             g.ntz = p2.ntz;
             g.nty = p2.nty;
             g.cx = p2.cx;
             g.nchunks = p2.nchunks;
             g.nblocks = p2.nblocks;
-            g.cap = kInjCap2x;
+            g.cap = step2_inj_cap(L.ndim == 3);
             g.tag = 2;
             InjGeom ge = g;   // first update: the extended tile and chunk
-            ge.ey = M;
+            ge.ey = my;
             ge.ez4 = hz;
             ge.ex = M;
             InjGeom gi = g;   // second update: the inner tile, numbered in the extended one
-            gi.oy = M;
+            gi.oy = my;
             gi.oz4 = hz;
             WF_TRY(inj[0].plan(md, pts, p, series, nt, md.d_inc[1], s, &ge));
             WF_TRY(inj[1].plan(md, pts, p, series, nt, md.d_inc[2], s, &gi));
@@ -425,7 +425,7 @@ struct TwoStep {
         count_step_launch(kModeCount);
         {
             ProfScope prof(WF_KERNEL_STEP2, q);
-            WF_TRY(hip_check(launch_step2(x, md.half, q), "two-update launch"));
+            WF_TRY(hip_check(launch_step2(x, md.L.ndim, md.half, q), "two-update launch"));
         }
         return throttle_tick(q);
     }

@@ -106,12 +106,44 @@ def test_two_step_many_blocks_and_receivers():
     assert torch.equal(d2, d1), float((d2 - d1).abs().max())
 
 
-def test_two_step_off_for_other_orders_and_2d():
-    """Orders other than 4 and 8, and 2D grids, keep one update per launch."""
-    for shape, k in (((30, 20, 40), 12), ((60, 70), 8)):
+def test_two_step_off_for_other_orders():
+    """Orders other than 4 and 8 keep one update per launch (2D and 3D)."""
+    for shape, k in (((30, 20, 40), 12), ((60, 70), 12), ((60, 70), 16)):
         P = make_problem(shape, 6, k, 6, seed=270 + k, nrec=20)
         _, n1, n2 = _forward(P, True)
         assert (n1, n2) == (6, 0)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("steps", [1, 2, 7, 12])
+def test_two_step_2d_equals_one_update_per_launch(k, steps):
+    """2D rows of 504-node tiles: 40 x 1100 physical nodes (3 z tiles, the
+    last ragged) with sources on tile, chunk and grid edges and more
+    receivers than blocks; records bitwise equal to one update per launch,
+    forward and adjoint; the forward record within the oracle's bar."""
+    from _harness import noise
+    P = make_problem((40, 1100), 8, k, steps, seed=350 + k + steps, nrec=300)
+    src, q = _scatter_sources(P, 20, seed=k + steps)
+    rec = np.vstack([P.rec_xyz, src])
+    prop = P.propagator()
+    d2, n1a, n2a = _forward(P, True, prop=prop, src=src, q=q, rec=rec)
+    d1, n1b, n2b = _forward(P, False, prop=prop, src=src, q=q, rec=rec)
+    assert (n2a, n1a) == (steps // 2, steps % 2), (n2a, n1a)
+    assert torch.equal(d2, d1), float((d2 - d1).abs().max())
+    y = noise(P.nt, rec.shape[0], P.dt, 15.0, 11 + steps).astype(np.float32)
+    x2, m2 = _adjoint(P, True, prop, rec, y, src)
+    x1, _ = _adjoint(P, False, prop, rec, y, src)
+    assert m2 == steps // 2
+    assert torch.equal(x2, x1), float((x2 - x1).abs().max())
+    if steps == 12:
+        check_record(d2.cpu().numpy(), _oracle_forward(P, src, q, rec),
+                     label="2D two updates per launch, order %d" % k)
+
+
+def _oracle_forward(P, src, q, rec):
+    import oracle
+    return oracle.forward(P.grid(), P.m64(), P.eta(), P.dt, P.nt, P.pts(src), q.astype(np.float64),
+                          P.pts(rec))
 
 
 def _adjoint(P, two, prop, rec, y, src):
