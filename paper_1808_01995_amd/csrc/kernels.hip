@@ -482,14 +482,16 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 }
 
 // ---------------------------------------------------------------------------
-// Two plain updates per pass (3D): temporal blocking over overlapping tiles.
+// Two plain updates per pass (2D and 3D): temporal blocking over overlapping
+// tiles.
 //
-// Block: EY = BY + 2M rows (3D; one row in 2D) of BZE threads, one float4 column each,
-// over the extended tile; the inner tile is rows [M, M + BY) and columns
-// [HZ, BZE - HZ). For its chunk [xb, xe) the block walks planes
-// x = xb - M .. xe + M - 1: every thread forms u^{n+1}(x) of its column from
-// a register ring of u^n planes (x taps) and an LDS plane of u^n that holds
-// the extended tile plus a frame of M rows and P nodes (y and z taps), and
+// Block: EY = BY + 2M rows (3D; one row in 2D) of BZE threads, one float4
+// column each, over the extended tile; the inner tile is rows [M, M + BY)
+// (3D) and columns [HZ, BZE - HZ). For its chunk [xb, xe) the block walks
+// planes x = xb - M .. xe + M - 1: every thread forms u^{n+1}(x) of its
+// column from a register ring of u^n planes (x taps) and an LDS plane of u^n
+// that holds the extended tile plus a frame of M rows (3D) and P nodes (y and
+// z taps), and
 // keeps it in a register ring of u^{n+1} planes; the inner threads then form
 // u^{n+2}(x - M) from that ring and an LDS plane of u^{n+1}(x - M), whose y
 // and z neighbours the extended tile holds. u^{n+1} is zero outside the grid
@@ -500,7 +502,7 @@ __global__ void __launch_bounds__(BZ * BY, (D3 && M <= 4) ? 3 : 1) k_step_batch(
 // ---------------------------------------------------------------------------
 // PF: planes the u^n ring prefetches; LA: planes of lookahead of u^{n-1} and
 // kap; KR: the second update reloads kap (else a register ring keeps M + 1
-// planes of it, LA = 1 only); NT: u^{n-1} and kap streamed non-temporal
+// planes of it, LA = 1 only); NTS: u^{n-1} and kap streamed non-temporal
 // (else cached, so that the overlapping rows of neighbouring blocks can hit).
 template <bool D3, int M, int BY, int BZE, int PF, int LA, bool KR, bool NTS>
 __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx) {
@@ -519,6 +521,9 @@ __device__ __forceinline__ void step2_body(const Step2Params& p, const int bidx)
     constexpr int HL = 2;                  // planes of lookahead of the frame loads
     static_assert(NQ % KQ == 0 && NQ % HL == 0 && NQ % LA == 0, "ring lengths must divide the unrolled loop");
     static_assert(KR || LA == 1, "the kap ring takes the next plane only");
+    // planes read beyond the chunk: u^n from xb - 2M to xe + 2M + PF - 1,
+    // u^{n-1} and kap from xb - 2M to xe + M + LA - 1: all within the ghost planes
+    static_assert(2 * M + PF <= kGhostPlanes && M + LA <= kGhostPlanes, "reads beyond the ghost planes");
     auto lds_ = [](const float* q) { return NTS ? ld4s(q) : ld4(q); };
     constexpr int NFY = 2 * MY * BZE;      // frame rows above and below (float4 loads)
     constexpr int NFZ = 2 * EY * HZ;       // frame columns left and right
