@@ -251,3 +251,22 @@ def test_two_step_small_and_exact_tile_grids(k, shape, nbl):
         d1, _, _ = _forward(P, False, prop=prop, src=src, q=q, rec=rec)
         assert n2 == steps // 2
         assert torch.equal(d2, d1), (shape, steps, float((d2 - d1).abs().max()))
+
+
+def test_two_step_falls_back_when_points_crowd_a_block():
+    """An adjoint whose 400 receivers crowd a few planes of one 2D row tile
+    (more injection entries than a block of the two-update kernel stages)
+    keeps one update per launch, with the same record."""
+    from _harness import noise
+    P = make_problem((40, 300), 8, 4, 8, seed=370, nrec=10)
+    rng = np.random.default_rng(5)
+    h = P.spacing[0]
+    rec = np.stack([rng.uniform(150.0, 150.0 + 3 * h, 400), rng.uniform(0.0, 2900.0, 400)], axis=1)
+    src = P.src_xyz
+    y = noise(P.nt, rec.shape[0], P.dt, 15.0, 4).astype(np.float32)
+    prop = P.propagator()
+    x2, n2 = _adjoint(P, True, prop, rec, y, src)
+    x1, _ = _adjoint(P, False, prop, rec, y, src)
+    assert n2 == 0
+    assert torch.equal(x2, x1)
+    assert float(x1.abs().max()) > 0
