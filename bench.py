@@ -642,6 +642,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed shots")
     ap.add_argument("--space-order", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-two-update", action="store_true",
+                    help="skip the short shots that compare two updates per launch with one "
+                         "(also skipped with --serve-requests 0)")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--extras", action="store_true", help="also time the adjoint shot")
     ap.add_argument("--rows", default="",
@@ -808,6 +811,16 @@ def main():
 
     prop.close()
     rows = run_rows(torch, args, orders, out)
+    if not args.no_two_update and args.serve_requests > 0 and "c3" not in rows and "2d" not in rows:
+        # the shots that run two updates per launch by default, each also
+        # with one: 592^3 order 4 and 8272^2 order 4 (short shots; part of
+        # the full default line, like the serving rows, so skipped with
+        # --serve-requests 0, the headline-only run the profiles are taken on)
+        try:
+            out["two_update"] = {"c3_order4": sweep_c3(torch, orders=(4,), steps=100),
+                                 "large_2d_order4": large_2d(torch, orders=(4,), steps=100)}
+        except Exception as e:  # must not hide the headline
+            out["two_update"] = {"error": str(e)}
     if "serve" in rows and args.serve_requests < 256:
         args.serve_requests = 256
     if args.serve_requests > 0:
