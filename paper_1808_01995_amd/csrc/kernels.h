@@ -11,7 +11,9 @@ namespace wf {
 constexpr int kMaxHalf = 8;   // space order up to 16
 
 // Number of zero ghost x-planes kept before and after every field that the
-// step kernel reads (it needs M + prefetch distance <= 10 of them).
+// step kernels read (one update per launch needs M + its prefetch distance,
+// at most 10; two updates per launch 2M + its prefetch distance, at most 9
+// for the compiled orders, checked at compile time).
 constexpr int kGhostPlanes = 12;
 
 // What the step kernel does besides the update (template variants).
