@@ -12,8 +12,10 @@ the timed region.
 Printed: one JSON line with the headline metric (grid-point updates per second
 on the computational grid), the roofline of the dominant kernel (HBM bound,
 16 algorithmic bytes per point per update against 8 TB/s) measured with HIP
-events inside the timed region, and the FP64 oracle timed on the host cores on
-a bounded sample of the same workload.
+events inside the timed region, the serving stream, short shots of the
+workloads that run two updates per launch by default (592^3 and 8272^2 at
+order 4, each also with one update per launch), and the FP64 oracle timed on
+the host cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
 """
