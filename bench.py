@@ -598,6 +598,41 @@ def profile_kernels(torch, steps=400):
     print(json.dumps({"profile_kernels": "done", "grid": list(p0.comp_shape), "updates": steps}), flush=True)
 
 
+def profile_two_update(torch, so, steps=20):
+    """A short run of the two-update kernel for rocprofv3: the C2 grid (336^3,
+    smooth random velocity) at space order `so`, `steps` updates with two
+    updates per launch forced (wf_two_step_enable(2))."""
+    from paper_1808_01995_amd import Propagator, _abi
+    from synthetic import config, ricker
+    c = config("c2_3d_so8", space_order=so, steps=steps)
+    prop = Propagator(c.velocity(), spacing=c.spacing, nbl=c.nbl, space_order=so)
+    dt = 0.5 * prop.critical_dt()
+    q = torch.from_numpy(ricker(c.nt, dt, c.f0_hz)[:, None].astype(np.float32)).cuda()
+    _abi.wf_two_step_enable(2)
+    rec = prop.forward(dt, c.nt, c.src, q, c.rec)
+    torch.cuda.synchronize()
+    _abi.wf_two_step_enable(1)
+    prop.close()
+    print(json.dumps({"profile_two_update": "done", "space_order": so, "updates": steps,
+                      "record_max": float(rec.abs().max())}), flush=True)
+
+
+def profile_team_shots(torch, shots=3):
+    """C1-size forward shots (101^2 physical + 20-node layer, order 4, 500
+    updates) submitted to the serving engine one after another, each run on
+    resident teams (WAVEFD_TEAM_WIDTH in the environment sets the split), for
+    rocprofv3 counters."""
+    from paper_1808_01995_amd.serve import Server, build_request, run_stream
+    reqs = [build_request({"ndim": 2, "n": 101, "space_order": 4, "steps": 500, "kind": "forward",
+                           "seed": 300 + i}, nbl=20) for i in range(shots)]
+    srv = Server(hbm_budget_bytes=4 << 30, max_slots=16)
+    for r in reqs:
+        run_stream(srv, [r])
+    srv.close()
+    print(json.dumps({"profile_team_shots": "done", "shots": shots,
+                      "team_width": os.environ.get("WAVEFD_TEAM_WIDTH")}), flush=True)
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10) -> float:
     """Read + write GB/s of a plain device-to-device copy (the STREAM-copy
     analogue the step kernel's bandwidth is compared with)."""
@@ -663,6 +698,10 @@ def main():
                          "short profiling runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-two-update", type=int, default=0, metavar="ORDER",
+                    help="short run of the two-update kernel at this space order on the C2 grid, for rocprofv3")
+    ap.add_argument("--profile-team-shots", action="store_true",
+                    help="three C1-size shots on the engine's resident teams, for rocprofv3")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the gradient and Born kernels for a profiler: 280^3 order 8, "
                          "400 updates, two store-all gradients and two Born modellings")
@@ -692,6 +731,12 @@ def main():
     from paper_1808_01995_amd import _abi
     if args.profile_kernels:
         profile_kernels(torch)
+        return
+    if args.profile_two_update:
+        profile_two_update(torch, args.profile_two_update)
+        return
+    if args.profile_team_shots:
+        profile_team_shots(torch)
         return
     orders = tuple(int(x) for x in args.orders.split(",") if x)
     if args.rows_only:
